@@ -1,0 +1,42 @@
+"""Compile the CPU oracle into ``oracle/liboracle.so`` with gcc.
+
+Test infrastructure: the product library never builds or loads this.
+Plain ``-O2`` without fast-math so that ``exp`` is the C library's.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = [os.path.join(HERE, "oracle.c")]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def sources():
+    return list(SRC) + sorted(
+        os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".c") and f != "oracle.c"
+    )
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-Wall",
+           "-o", LIB + ".tmp"] + sources() + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def ensure_built() -> str:
+    """Build only if the library is missing or older than a source file."""
+    if os.path.exists(LIB):
+        t = os.path.getmtime(LIB)
+        if all(os.path.getmtime(s) <= t for s in sources()):
+            return LIB
+    return build()
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,225 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle, tests and bench.
+
+This module holds none of the sweep's arithmetic: it only draws the per-grain
+quantities that the workloads are defined by (Schmid factors, bulk energies,
+temperatures, lattice sizes, seeds) with numpy's PCG64, and quantises the
+energies to the 2^-16 fixed point both paths consume.  The random numbers the
+method itself draws (Voronoi seed points, Metropolis trials) come from each
+side's own Philox implementation, keyed by the seeds given here.
+
+Workloads (all synthetic, shaped after the paper's experiments: square and
+cubic periodic lattices, Voronoi polycrystals, per-orientation bulk energies):
+
+  voronoi_2d_64      64x64 VN4, int32, 40 grains, zero bulk energy, kT 0.5,
+                     100 MCS, seeds 1.
+  schmid_2d_1024     1024x1024 VN4, int16, 2000 grains, m_g ~ U[0.27,0.5]
+                     (PCG64 2002), E_g = 0.2 m_g, kT 0.5, 1000 MCS, seeds 2.
+  schmid_3d_256      256^3 VN6, int16, 20000 grains, Schmid factor of a
+                     uniform SO(3) orientation (Shoemake, PCG64 3003) under a
+                     [001] load, E_g = 0.15 m_g, kT 0.6, 500 MCS, seeds 3.
+  ensemble_moore8    64 Moore-8 lattices, sides in {128,...,1024}, 50..2000
+                     grains, kT ~ U[0.3,1.0], energies as schmid_2d_1024,
+                     1000 MCS (PCG64 4004), seeds 40000+j / 4000+j.
+"""
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+VN4, MOORE8, VN6, MOORE26 = 0, 1, 2, 3
+I16, I32 = 0, 1
+
+FIXED_ONE = 65536  # 2^16: energies are stored as int32 multiples of 2^-16
+
+
+def quantise(E):
+    """Energy -> int32 in 2^-16 units, rounding half to even."""
+    return np.rint(np.asarray(E, dtype=np.float64) * FIXED_ONE).astype(np.int32)
+
+
+# ---------------------------------------------------------------- Schmid
+
+def fcc_slip_systems():
+    """The 12 FCC {111}<110> slip systems as unit (normal, direction) pairs."""
+    normals = [(1, 1, 1), (-1, 1, 1), (1, -1, 1), (1, 1, -1)]
+    dirs = [(1, -1, 0), (1, 0, -1), (0, 1, -1), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    n_out, d_out = [], []
+    for n in normals:
+        n = np.asarray(n, dtype=np.float64)
+        for d in dirs:
+            d = np.asarray(d, dtype=np.float64)
+            if abs(float(n @ d)) < 1e-12:
+                n_out.append(n / np.linalg.norm(n))
+                d_out.append(d / np.linalg.norm(d))
+    return np.asarray(n_out), np.asarray(d_out)
+
+
+def schmid_factor(load_axes):
+    """max over the 12 systems of |l.n||l.d| for unit load axes l (crystal frame)."""
+    l = np.atleast_2d(np.asarray(load_axes, dtype=np.float64))
+    l = l / np.linalg.norm(l, axis=1, keepdims=True)
+    n, d = fcc_slip_systems()
+    return np.max(np.abs(l @ n.T) * np.abs(l @ d.T), axis=1)
+
+
+def shoemake_quaternions(rng, count):
+    """Uniform random unit quaternions (w, x, y, z), Shoemake's method."""
+    u1, u2, u3 = rng.random(count), rng.random(count), rng.random(count)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    x, y = a * np.sin(2 * np.pi * u2), a * np.cos(2 * np.pi * u2)
+    z, w = b * np.sin(2 * np.pi * u3), b * np.cos(2 * np.pi * u3)
+    return np.stack([w, x, y, z], axis=1)
+
+
+def quat_to_matrix(q):
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((q.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z); R[:, 0, 1] = 2 * (x * y - z * w); R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w); R[:, 1, 1] = 1 - 2 * (x * x + z * z); R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w); R[:, 2, 1] = 2 * (y * z + x * w); R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def matrix_to_bunge(R):
+    """Bunge ZXZ Euler angles (phi1, Phi, phi2) of passive rotation matrices."""
+    Phi = np.arccos(np.clip(R[:, 2, 2], -1.0, 1.0))
+    phi1 = np.arctan2(R[:, 2, 0], -R[:, 2, 1])
+    phi2 = np.arctan2(R[:, 0, 2], R[:, 1, 2])
+    small = np.abs(np.sin(Phi)) < 1e-9
+    phi1 = np.where(small, np.arctan2(R[:, 0, 1], R[:, 0, 0]), phi1)
+    phi2 = np.where(small, 0.0, phi2)
+    return np.stack([np.mod(phi1, 2 * np.pi), Phi, np.mod(phi2, 2 * np.pi)], axis=1)
+
+
+def bunge_to_matrix(e):
+    """Passive (sample -> crystal) rotation from Bunge ZXZ angles."""
+    e = np.atleast_2d(np.asarray(e, dtype=np.float64))
+    c1, s1 = np.cos(e[:, 0]), np.sin(e[:, 0])
+    c, s = np.cos(e[:, 1]), np.sin(e[:, 1])
+    c2, s2 = np.cos(e[:, 2]), np.sin(e[:, 2])
+    g = np.empty((e.shape[0], 3, 3))
+    g[:, 0, 0] = c1 * c2 - s1 * s2 * c; g[:, 0, 1] = s1 * c2 + c1 * s2 * c; g[:, 0, 2] = s2 * s
+    g[:, 1, 0] = -c1 * s2 - s1 * c2 * c; g[:, 1, 1] = -s1 * s2 + c1 * c2 * c; g[:, 1, 2] = c2 * s
+    g[:, 2, 0] = s1 * s; g[:, 2, 1] = -c1 * s; g[:, 2, 2] = c
+    return g
+
+
+def schmid_bins(m, lo=0.27, width=0.01, n_bins=23):
+    """Grain -> Schmid-factor bin (23 bins of 0.01 on [0.27, 0.50])."""
+    b = np.floor((np.asarray(m) - lo) / width).astype(np.int64)
+    return np.clip(b, 0, n_bins - 1).astype(np.int32)
+
+
+# -------------------------------------------------------------- workloads
+
+@dataclass
+class Workload:
+    name: str
+    dims: tuple               # (Lx, Ly) or (Lx, Ly, Lz), x fastest
+    nbr: int
+    spin: int
+    n_grains: int
+    kT: float
+    n_mcs: int
+    voronoi_seed: int
+    sweep_seed: int
+    B: np.ndarray             # int32[n_grains], 2^-16 units
+    m: Optional[np.ndarray] = None      # Schmid factor per grain
+    euler: Optional[np.ndarray] = None  # Bunge angles per grain
+    n_bins: int = 23
+    J_fx: int = FIXED_ONE
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ndim(self):
+        return len(self.dims)
+
+    @property
+    def n_sites(self):
+        return int(np.prod(self.dims))
+
+    @property
+    def spin_dtype(self):
+        return np.int16 if self.spin == I16 else np.int32
+
+    @property
+    def grain_bin(self):
+        if self.m is None:
+            return np.full(self.n_grains, -1, dtype=np.int32)
+        return schmid_bins(self.m, n_bins=self.n_bins)
+
+    @property
+    def colours(self):
+        return {VN4: 2, MOORE8: 4, VN6: 2, MOORE26: 8}[self.nbr]
+
+
+def voronoi_2d_64():
+    G = 40
+    return Workload("voronoi_2d_64", (64, 64), VN4, I32, G, 0.5, 100, 1, 1,
+                    np.zeros(G, dtype=np.int32), n_bins=0)
+
+
+def schmid_2d(side=1024, G=2000, seed=2002, n_mcs=1000, vseed=2, sseed=2, kT=0.5, name=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = 0.27 + 0.23 * rng.random(G)
+    return Workload(name or f"schmid_2d_{side}", (side, side), VN4, I16, G, kT, n_mcs, vseed, sseed,
+                    quantise(0.2 * m), m=m)
+
+
+def schmid_2d_1024():
+    return schmid_2d(name="schmid_2d_1024")
+
+
+def schmid_3d(side=256, G=20000, seed=3003, n_mcs=500, vseed=3, sseed=3, kT=0.6, name=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = quat_to_matrix(shoemake_quaternions(rng, G))   # passive: crystal = g . sample
+    load = g @ np.array([0.0, 0.0, 1.0])        # [001] load axis in the crystal frame
+    m = schmid_factor(load)
+    return Workload(name or f"schmid_3d_{side}", (side, side, side), VN6, I16, G, kT, n_mcs, vseed,
+                    sseed, quantise(0.15 * m), m=m, euler=matrix_to_bunge(g))
+
+
+def schmid_3d_256():
+    return schmid_3d(name="schmid_3d_256")
+
+
+def ensemble_moore8(count=64, seed=4004, n_mcs=1000):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.choice(np.array([128, 256, 512, 1024]), size=count)
+    Gs = rng.integers(50, 2001, size=count)
+    kTs = rng.uniform(0.3, 1.0, size=count).astype(np.float32)
+    out: List[Workload] = []
+    for j in range(count):
+        m = 0.27 + 0.23 * rng.random(int(Gs[j]))
+        side = int(sides[j])
+        out.append(Workload(f"ensemble_moore8[{j}]", (side, side), MOORE8, I16, int(Gs[j]),
+                            float(kTs[j]), n_mcs, 40000 + j, 4000 + j, quantise(0.2 * m), m=m))
+    return out
+
+
+# ------------------------------------------------- paper-shaped test inputs
+
+def circle_grain(side=256, radius=80.0):
+    """Q=2 bicrystal: a disc of spin 1 centred in a periodic square of spin 0
+    (Sec. 4, first validation case, scaled down)."""
+    y, x = np.mgrid[0:side, 0:side]
+    c = (side - 1) / 2.0
+    return ((x - c) ** 2 + (y - c) ** 2 <= radius ** 2).astype(np.int32)
+
+
+def flat_strip(Lx=128, Ly=256):
+    """Q=2 periodic strip with two flat (10) boundaries at y = Ly/4, 3Ly/4."""
+    s = np.zeros((Ly, Lx), dtype=np.int32)
+    s[Ly // 4: 3 * Ly // 4, :] = 1
+    return s
+
+
+def gaussian_orientation_energy(n_orient=91, width=46.0):
+    """Eq. (9): b(n) = (32 pi)^-1/2 exp(-(n-46)^2 / (2 width^2)), n = 1..91."""
+    n = np.arange(1, n_orient + 1, dtype=np.float64)
+    return (32 * np.pi) ** -0.5 * np.exp(-((n - 46.0) ** 2) / (2 * width ** 2))
+
+
+def random_spins(dims, Q, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, Q, size=tuple(reversed(dims))).astype(np.int32)
