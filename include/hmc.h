@@ -1,0 +1,180 @@
+/*
+ * hmc.h -- C ABI of libhmc, the MI355X (gfx950) implementation of the
+ * red/black Q-state Potts sweep with a per-grain bulk energy.
+ *
+ * The method: Zhang, Dingreville, Bartel, Lusk, "Hybrid Monte Carlo
+ * simulation of stress-induced texture evolution with inelastic effects"
+ * (arXiv:1007.3509).
+ *   Sec. 3, Eq. (7): H = sum over sites and their M neighbours of the bond
+ *     energy plus a bulk energy b_i per site.  Bonds cost J between unlike
+ *     spins (J(1-delta), each bond once); b_i = b(q_i) is a property of the
+ *     grain (Sec. 6: a swept site inherits the overtaking grain's stored
+ *     dislocation energy).
+ *   Sec. 3: a trial flip is accepted with a probability that depends on the
+ *     change of H (Metropolis, min(1, exp(-dE/kT))).
+ *   Sec. 4: Red/Black updating -- one colour class per half step, no state
+ *     changes until the half step is over.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an hmc_status; nothing throws across the ABI.
+ *     On failure hmc_last_error() gives a message (thread-local, valid until
+ *     the next hmc_* call on the same thread).
+ *   - Arguments are validated on the host before any device work, so invalid
+ *     input never reaches a kernel.
+ *   - Spins: x fastest, row-major, periodic, values 0..Q-1 (Q = n_grains),
+ *     int16 (Q <= 32767) or int32.  Every side even and >= 4; N < 2^32.
+ *   - Energies: int32 in units of 2^-16 (J_fx = 65536*J; B[q] = b(q)*65536).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with
+ *     key = (lo32(seed), hi32(seed)), counter = (site, mcs, colour, 0).
+ *     Word 0 picks the trial spin, word 1 decides acceptance.
+ *   - Acceptance is integer: d = J_fx*(c(q) - c(q')) + B[q'] - B[q]
+ *     (c(s) = number of neighbours holding s); accept iff d <= 0 or
+ *     r1 < T(d) = min(2^32-1, floor(2^32 exp(-d / (65536 kT)))), T built on
+ *     the host in double precision with the C library exp.
+ *   - Neighbour order: VN4 +x,-x,+y,-y; VN6 adds +z,-z; Moore8 adds
+ *     (+1,+1),(-1,-1),(+1,-1),(-1,+1); Moore26 (dx,dy,dz) in {-1,0,1}^3\{0}
+ *     lexicographic in (dz,dy,dx).  Colours: VN4 (x+y)&1, VN6 (x+y+z)&1,
+ *     Moore8 (x&1)|(y&1)<<1, Moore26 (x&1)|(y&1)<<1|(z&1)<<2, passes
+ *     c = 0..C-1 every MC step.
+ *   - Determinism: final spins are a function of (initial spins, B, kT, seed,
+ *     starting MC step, neighbourhood, trial mode, J_fx) only -- not of the
+ *     tiling, the launch split, or how n_mcs is divided between calls.
+ *   - Streams: a lattice is bound to one HIP stream (NULL: the library makes
+ *     its own).  hmc_sweep is asynchronous; calls that return data to the host
+ *     synchronise that stream.  A handle is not thread-safe; distinct handles
+ *     are independent.
+ *   - Ownership: *_create / *_init allocate, *_free releases.  Host arrays
+ *     passed in are copied before return.  Output buffers belong to the caller.
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hmc_status;
+enum {
+    HMC_OK = 0,
+    HMC_E_INVAL = -1,    /* bad argument (null pointer, size, enum, range) */
+    HMC_E_NOMEM = -2,    /* device allocation failed or HMC_MAX_BYTES exceeded */
+    HMC_E_DEVICE = -3,   /* a HIP call failed (message carries hipGetErrorString) */
+    HMC_E_RANGE = -4,    /* an energy change could leave int32, or a table is too large */
+    HMC_E_STATE = -5,    /* handle in the wrong state (e.g. ensemble member changed) */
+    HMC_E_INTERNAL = -6
+};
+
+enum { HMC_VN4 = 0, HMC_MOORE8 = 1, HMC_VN6 = 2, HMC_MOORE26 = 3 };   /* C = 2, 4, 2, 8 */
+enum { HMC_I16 = 0, HMC_I32 = 1 };
+/* Trial spin.  NEIGHBOUR (production): the spin of a neighbour picked by
+ * word 0.  UNIFORM (test mode): q' = (q + 1 + floor(r0*(Q-1)/2^32)) mod Q,
+ * a symmetric proposal under which the Boltzmann distribution of Eq. (7)
+ * is invariant.  The paper does not name the trial rule (Sec. 3). */
+enum { HMC_PROP_NEIGHBOUR = 0, HMC_PROP_UNIFORM = 1 };
+
+typedef struct {
+    int32_t ndim;       /* 2 (VN4, Moore8) or 3 (VN6, Moore26) */
+    int32_t dims[3];    /* Lx, Ly, Lz (Lz ignored for ndim 2); even, >= 4 */
+    int32_t nbr;        /* HMC_VN4 .. HMC_MOORE26 */
+    int32_t spin;       /* HMC_I16 or HMC_I32 */
+    int32_t proposal;   /* HMC_PROP_NEIGHBOUR or HMC_PROP_UNIFORM */
+    int32_t J_fx;       /* 65536 * J, in [1, 2^24] */
+} hmc_lattice_desc;
+
+typedef struct hmc_lattice_s hmc_lattice;
+
+/* Library version of this header's ABI (incremented on any change). */
+int32_t hmc_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hmc_last_error(void);
+
+/* Number of HIP devices visible (0 without a GPU); never fails. */
+int32_t hmc_device_count(void);
+
+/* Allocate a lattice with all spins 0, bulk energies 0 and MC step 0.
+ * n_grains = Q, the number of spin values (1..32767 for int16, 1..2^31-1
+ * for int32).  stream: a hipStream_t, or NULL for a library-owned stream.
+ * Errors: INVAL (desc, sizes, Q), NOMEM, DEVICE. */
+hmc_status hmc_lattice_create(const hmc_lattice_desc *desc, int32_t n_grains, void *stream,
+                              hmc_lattice **out);
+
+/* As hmc_lattice_create, then the initial microstructure (the paper does not
+ * specify one; a seeded Voronoi tessellation is used): point g has fixed-point
+ * coordinates X_k = floor(r_k * 256 L_k / 2^32) from Philox(counter =
+ * (g, 0, 0, 0x564F524E), key = voronoi_seed); site x sits at 256 x; every
+ * site takes the index of the nearest point under periodic squared distance
+ * (integers), ties to the lower index.  Grains may be empty. */
+hmc_status hmc_lattice_init(const hmc_lattice_desc *desc, int32_t n_grains, uint64_t voronoi_seed,
+                            void *stream, hmc_lattice **out);
+
+/* Release a lattice (synchronises its stream first).  NULL is a no-op. */
+hmc_status hmc_lattice_free(hmc_lattice *L);
+
+/* Per-grain bulk energy b(q) of Eq. (7) in 2^-16 units (Sec. 6: carried by
+ * the grain).  B_fx: int32[n_grains], host memory (on_device = 0) or device
+ * memory (on_device = 1); copied.  n_grains must equal the lattice's Q.
+ * Errors: INVAL; RANGE if |J_fx|*M + 2 max|B| >= 2^31. */
+hmc_status hmc_set_grain_energy(hmc_lattice *L, const int32_t *B_fx, int32_t n_grains, int32_t on_device);
+
+/* n_mcs Monte Carlo steps of red/black Metropolis (Sec. 4) at temperature
+ * kT (the paper's effective temperature alpha_mc with J = 1), drawing from
+ * the Philox stream of `seed`.  Steps are numbered from the lattice's MC
+ * counter, which advances by n_mcs.  Asynchronous on the lattice's stream.
+ * Errors: INVAL (kT <= 0 or not finite, n_mcs < 0), RANGE (table cap),
+ * NOMEM, DEVICE. */
+hmc_status hmc_sweep(hmc_lattice *L, float kT, int32_t n_mcs, uint64_t seed);
+
+/* Grain statistics of the current spins (the texture the paper follows over
+ * time, Sec. 5): n_grains = number of spin values present; mean area =
+ * N / n_grains; frac[b] = sum of the areas of grains with grain_bin[q] == b,
+ * divided by N.  grain_bin: int32[Q] host array with values in [-1, n_bins)
+ * (-1 = leave the grain out); may be NULL when n_bins == 0.  frac_out:
+ * double[n_bins].  Synchronous.  Errors: INVAL, DEVICE. */
+hmc_status hmc_texture_stats(hmc_lattice *L, const int32_t *grain_bin, int32_t n_bins,
+                             int32_t *n_grains_out, double *mean_area_out, double *frac_out);
+
+/* Area (site count) of every spin value 0..Q-1 into int64[Q].  Synchronous. */
+hmc_status hmc_grain_areas(hmc_lattice *L, int64_t *areas_out);
+
+/* Copy the spins to / from host memory (bytes must equal N * spin size).
+ * set_spins rejects values outside [0, Q).  Synchronous. */
+hmc_status hmc_get_spins(hmc_lattice *L, void *host_dst, uint64_t bytes);
+hmc_status hmc_set_spins(hmc_lattice *L, const void *host_src, uint64_t bytes);
+
+/* Device-side checkpoint: snapshot copies spins and the MC counter into a
+ * buffer the lattice owns; restore copies them back.  Asynchronous.
+ * restore without a snapshot: STATE. */
+hmc_status hmc_snapshot(hmc_lattice *L);
+hmc_status hmc_restore(hmc_lattice *L);
+
+/* MC step counter (the second Philox counter word); checkpoint / resume. */
+hmc_status hmc_get_mcs(const hmc_lattice *L, uint64_t *mcs);
+hmc_status hmc_set_mcs(hmc_lattice *L, uint64_t mcs);
+
+/* Tiling of the sweep kernel: interior tile (tx, ty, tz) and MC steps fused
+ * per launch.  Zero means "choose automatically".  Each tile side must be an
+ * even divisor of the lattice side; the LDS box (tile + halo of
+ * mcs_per_launch * C sites per side) must fit the kernel's LDS budget.
+ * Results do not depend on the tiling.  get_tiling returns the tiling in
+ * force as int32[4]. */
+hmc_status hmc_set_tiling(hmc_lattice *L, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch);
+hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
+
+/* Kernel timing with HIP events recorded around every sweep launch on the
+ * lattice's stream.  profile_read synchronises, returns the summed kernel
+ * time, the number of launches and the site updates they performed since
+ * profiling was enabled (or last read), and resets the sums. */
+hmc_status hmc_profile(hmc_lattice *L, int32_t enable);
+hmc_status hmc_profile_read(hmc_lattice *L, double *kernel_ms, int64_t *launches, int64_t *site_updates);
+
+/* Wait for all work queued on the lattice's stream. */
+hmc_status hmc_synchronize(hmc_lattice *L);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_H */

@@ -1,0 +1,287 @@
+"""Python binding of libhmc (include/hmc.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method; all of it runs in the HIP library.  If the library
+is not built the import still works but the first call raises, loudly --
+there is no CPU fallback.
+
+The method is the red/black Q-state Potts sweep with a per-grain bulk energy
+of Zhang, Dingreville, Bartel & Lusk (arXiv:1007.3509), Sec. 3 Eq. (7) and
+Sec. 4.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhmc.so")
+
+HMC_OK, HMC_E_INVAL, HMC_E_NOMEM, HMC_E_DEVICE, HMC_E_RANGE, HMC_E_STATE, HMC_E_INTERNAL = 0, -1, -2, -3, -4, -5, -6
+HMC_VN4, HMC_MOORE8, HMC_VN6, HMC_MOORE26 = 0, 1, 2, 3
+HMC_I16, HMC_I32 = 0, 1
+HMC_PROP_NEIGHBOUR, HMC_PROP_UNIFORM = 0, 1
+
+NDIM = {HMC_VN4: 2, HMC_MOORE8: 2, HMC_VN6: 3, HMC_MOORE26: 3}
+COLOURS = {HMC_VN4: 2, HMC_MOORE8: 4, HMC_VN6: 2, HMC_MOORE26: 8}
+
+_STATUS = {0: "HMC_OK", -1: "HMC_E_INVAL", -2: "HMC_E_NOMEM", -3: "HMC_E_DEVICE", -4: "HMC_E_RANGE",
+           -5: "HMC_E_STATE", -6: "HMC_E_INTERNAL"}
+
+
+class HmcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class hmc_lattice_desc(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("dims", C.c_int32 * 3), ("nbr", C.c_int32), ("spin", C.c_int32),
+                ("proposal", C.c_int32), ("J_fx", C.c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("hmc_abi_version", C.c_int32, []),
+    ("hmc_last_error", C.c_char_p, []),
+    ("hmc_device_count", C.c_int32, []),
+    ("hmc_lattice_create", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("hmc_lattice_init", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_uint64, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    ("hmc_lattice_free", C.c_int32, [C.c_void_p]),
+    ("hmc_set_grain_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_sweep", C.c_int32, [C.c_void_p, C.c_float, C.c_int32, C.c_uint64]),
+    ("hmc_texture_stats", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double), C.c_void_p]),
+    ("hmc_grain_areas", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("hmc_get_spins", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64]),
+    ("hmc_set_spins", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64]),
+    ("hmc_snapshot", C.c_int32, [C.c_void_p]),
+    ("hmc_restore", C.c_int32, [C.c_void_p]),
+    ("hmc_get_mcs", C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("hmc_set_mcs", C.c_int32, [C.c_void_p, C.c_uint64]),
+    ("hmc_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    ("hmc_get_tiling", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("hmc_profile", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("hmc_profile_read", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
+    ("hmc_synchronize", C.c_int32, [C.c_void_p]),
+]
+
+
+def lib():
+    """The loaded libhmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libhmc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return [s[0] for s in _SIGS]
+
+
+def _check(status):
+    if status != HMC_OK:
+        raise HmcError(status, lib().hmc_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_desc(dims, nbr, spin=HMC_I16, proposal=HMC_PROP_NEIGHBOUR, J_fx=65536):
+    d = hmc_lattice_desc()
+    d.ndim = len(dims)
+    for a in range(3):
+        d.dims[a] = int(dims[a]) if a < len(dims) else 1
+    d.nbr, d.spin, d.proposal, d.J_fx = int(nbr), int(spin), int(proposal), int(J_fx)
+    return d
+
+
+# ----------------------------------------------------------- C entry points
+
+def hmc_abi_version():
+    return lib().hmc_abi_version()
+
+
+def hmc_device_count():
+    return lib().hmc_device_count()
+
+
+def hmc_lattice_create(desc, n_grains, stream=None):
+    h = C.c_void_p()
+    _check(lib().hmc_lattice_create(C.byref(desc), int(n_grains), stream, C.byref(h)))
+    return h
+
+
+def hmc_lattice_init(desc, n_grains, voronoi_seed, stream=None):
+    h = C.c_void_p()
+    _check(lib().hmc_lattice_init(C.byref(desc), int(n_grains), int(voronoi_seed), stream, C.byref(h)))
+    return h
+
+
+def hmc_lattice_free(h):
+    _check(lib().hmc_lattice_free(h))
+
+
+def hmc_set_grain_energy(h, B_fx):
+    b = np.ascontiguousarray(np.asarray(B_fx, dtype=np.int32))
+    _check(lib().hmc_set_grain_energy(h, _ptr(b), int(b.size), 0))
+
+
+def hmc_sweep(h, kT, n_mcs, seed):
+    _check(lib().hmc_sweep(h, float(kT), int(n_mcs), int(seed)))
+
+
+def hmc_texture_stats(h, grain_bin=None, n_bins=0):
+    ng = C.c_int32()
+    mean = C.c_double()
+    frac = np.zeros(max(int(n_bins), 1), dtype=np.float64)
+    gb = None if grain_bin is None else np.ascontiguousarray(np.asarray(grain_bin, dtype=np.int32))
+    _check(lib().hmc_texture_stats(h, None if gb is None else _ptr(gb), int(n_bins), C.byref(ng), C.byref(mean),
+                                   _ptr(frac)))
+    return int(ng.value), float(mean.value), frac[:int(n_bins)].copy()
+
+
+def hmc_grain_areas(h, n_grains):
+    out = np.empty(int(n_grains), dtype=np.int64)
+    _check(lib().hmc_grain_areas(h, _ptr(out)))
+    return out
+
+
+def hmc_get_spins(h, shape, dtype):
+    out = np.empty(shape, dtype=dtype)
+    _check(lib().hmc_get_spins(h, _ptr(out), out.nbytes))
+    return out
+
+
+def hmc_set_spins(h, spins):
+    s = np.ascontiguousarray(spins)
+    _check(lib().hmc_set_spins(h, _ptr(s), s.nbytes))
+
+
+def hmc_snapshot(h):
+    _check(lib().hmc_snapshot(h))
+
+
+def hmc_restore(h):
+    _check(lib().hmc_restore(h))
+
+
+def hmc_get_mcs(h):
+    v = C.c_uint64()
+    _check(lib().hmc_get_mcs(h, C.byref(v)))
+    return int(v.value)
+
+
+def hmc_set_mcs(h, mcs):
+    _check(lib().hmc_set_mcs(h, int(mcs)))
+
+
+def hmc_set_tiling(h, tx=0, ty=0, tz=0, mcs_per_launch=0):
+    _check(lib().hmc_set_tiling(h, int(tx), int(ty), int(tz), int(mcs_per_launch)))
+
+
+def hmc_get_tiling(h):
+    out = np.zeros(4, dtype=np.int32)
+    _check(lib().hmc_get_tiling(h, _ptr(out)))
+    return tuple(int(v) for v in out)
+
+
+def hmc_profile(h, enable=True):
+    _check(lib().hmc_profile(h, int(bool(enable))))
+
+
+def hmc_profile_read(h):
+    ms = C.c_double()
+    n = C.c_int64()
+    su = C.c_int64()
+    _check(lib().hmc_profile_read(h, C.byref(ms), C.byref(n), C.byref(su)))
+    return float(ms.value), int(n.value), int(su.value)
+
+
+def hmc_synchronize(h):
+    _check(lib().hmc_synchronize(h))
+
+
+# --------------------------------------------------------- convenience class
+
+class Lattice:
+    """Owns one hmc_lattice handle (same calls, numpy in and out)."""
+
+    def __init__(self, dims, nbr, n_grains, voronoi_seed=None, spin=HMC_I16, proposal=HMC_PROP_NEIGHBOUR,
+                 J_fx=65536, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.nbr, self.spin, self.n_grains = int(nbr), int(spin), int(n_grains)
+        self.dtype = np.int16 if spin == HMC_I16 else np.int32
+        desc = make_desc(self.dims, nbr, spin, proposal, J_fx)
+        if voronoi_seed is None:
+            self.h = hmc_lattice_create(desc, n_grains, stream)
+        else:
+            self.h = hmc_lattice_init(desc, n_grains, voronoi_seed, stream)
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.dims))
+
+    def set_grain_energy(self, B_fx):
+        hmc_set_grain_energy(self.h, B_fx)
+
+    def sweep(self, kT, n_mcs, seed):
+        hmc_sweep(self.h, kT, n_mcs, seed)
+
+    def spins(self):
+        return hmc_get_spins(self.h, self.shape, self.dtype)
+
+    def set_spins(self, s):
+        hmc_set_spins(self.h, np.asarray(s, dtype=self.dtype).reshape(self.shape))
+
+    def texture_stats(self, grain_bin=None, n_bins=0):
+        return hmc_texture_stats(self.h, grain_bin, n_bins)
+
+    def grain_areas(self):
+        return hmc_grain_areas(self.h, self.n_grains)
+
+    @property
+    def mcs(self):
+        return hmc_get_mcs(self.h)
+
+    @mcs.setter
+    def mcs(self, v):
+        hmc_set_mcs(self.h, v)
+
+    def set_tiling(self, tx=0, ty=0, tz=0, mcs_per_launch=0):
+        hmc_set_tiling(self.h, tx, ty, tz, mcs_per_launch)
+
+    def tiling(self):
+        return hmc_get_tiling(self.h)
+
+    def synchronize(self):
+        hmc_synchronize(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            hmc_lattice_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

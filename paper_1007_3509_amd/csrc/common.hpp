@@ -1,0 +1,184 @@
+// common.hpp -- internal declarations shared by the libhmc translation units.
+//
+// Nothing here is part of the ABI (include/hmc.h is).  The lattice object,
+// error plumbing, device-memory accounting and the Philox4x32-10 generator
+// (Salmon, Moraes, Dror, Shaw, SC'11) used by both the host (Voronoi seed
+// points) and the kernels (Metropolis trials).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hmc.h"
+
+namespace hmc {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string& msg);
+hmc_status fail(hmc_status code, const std::string& msg);
+hmc_status hip_fail(hipError_t e, const char* what);
+
+#define HMC_HIP(call)                                             \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::hmc::hip_fail(e_, #call);  \
+    } while (0)
+
+#define HMC_TRY(call)                         \
+    do {                                      \
+        hmc_status s_ = (call);               \
+        if (s_ != HMC_OK) return s_;          \
+    } while (0)
+
+// Device allocation with the optional HMC_MAX_BYTES cap.
+hmc_status dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void* p, size_t bytes);
+
+// ------------------------------------------------------------------ Philox
+
+struct Philox2 {   // the two words the sweep consumes
+    uint32_t r0, r1;
+};
+
+// Philox4x32-10: ten rounds of two 32x32->64 products on counter words 0 and
+// 2 with the round key mixed into the high halves; Weyl key schedule.
+__host__ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                       uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ Philox2 philox_r01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1) {
+    uint32_t o[4];
+    philox4x32_10(c0, c1, c2, c3, k0, k1, o);
+    return Philox2{o[0], o[1]};
+}
+
+// --------------------------------------------------------------- geometry
+
+struct NbrInfo {
+    int M;      // neighbours
+    int C;      // colours
+    int ndim;
+};
+NbrInfo nbr_info(int nbr);
+
+// Offsets (dx, dy, dz) of neighbour k in the fixed trial order:
+// VN4 +x,-x,+y,-y; VN6 adds +z,-z; Moore8 adds (+1,+1),(-1,-1),(+1,-1),(-1,+1);
+// Moore26 runs over {-1,0,1}^3 without the centre, lexicographic in (dz,dy,dx).
+__host__ __device__ constexpr int nbr_dx(int nbr, int k) {
+    if (nbr == HMC_MOORE26) return ((k < 13 ? k : k + 1) % 3) - 1;
+    if (k == 0) return 1;
+    if (k == 1) return -1;
+    if (nbr == HMC_MOORE8 && (k == 4 || k == 6)) return 1;
+    if (nbr == HMC_MOORE8 && (k == 5 || k == 7)) return -1;
+    return 0;
+}
+__host__ __device__ constexpr int nbr_dy(int nbr, int k) {
+    if (nbr == HMC_MOORE26) return (((k < 13 ? k : k + 1) / 3) % 3) - 1;
+    if (k == 2) return 1;
+    if (k == 3) return -1;
+    if (nbr == HMC_MOORE8 && (k == 4 || k == 7)) return 1;
+    if (nbr == HMC_MOORE8 && (k == 5 || k == 6)) return -1;
+    return 0;
+}
+__host__ __device__ constexpr int nbr_dz(int nbr, int k) {
+    if (nbr == HMC_MOORE26) return ((k < 13 ? k : k + 1) / 9) - 1;
+    if (nbr == HMC_VN6 && k == 4) return 1;
+    if (nbr == HMC_VN6 && k == 5) return -1;
+    return 0;
+}
+
+// ----------------------------------------------------- threshold table
+
+// T(d) for every d > 0 the lattice can produce, laid out as
+// T[(dn - dn_lo) * TW + (dB + R)] with dn = c(q) - c(q'), dB = B[q'] - B[q],
+// R = max B - min B, TW = 2R + 1.
+struct Table {
+    uint32_t* dev = nullptr;
+    size_t bytes = 0;
+    int32_t dn_lo = 0, rows = 0, R = 0, TW = 1;
+    uint32_t kT_bits = 0;
+    int32_t Bmin = 0, Bmax = 0;
+    bool valid = false;
+};
+uint32_t threshold_value(int64_t d, float kT);
+hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax,
+                       hipStream_t stream);
+void free_table(Table& tab);
+
+// ---------------------------------------------------------------- tiling
+
+struct Tiling {
+    int32_t tx = 0, ty = 0, tz = 0, k = 0;   // interior tile, MC steps per launch (0: automatic)
+};
+
+// --------------------------------------------------------------- lattice
+
+}  // namespace hmc
+
+struct hmc_lattice_s {
+    hmc_lattice_desc desc{};
+    int32_t Q = 0;
+    int64_t N = 0;
+    int M = 0, C = 0, ndim = 0;
+    size_t spin_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+
+    void* spins[2] = {nullptr, nullptr};
+    int cur = 0;
+    void* snap = nullptr;
+    uint64_t snap_mcs = 0;
+    bool has_snap = false;
+    uint64_t mcs = 0;
+
+    int32_t* dB = nullptr;
+    std::vector<int32_t> hB;
+    int32_t Bmin = 0, Bmax = 0;
+    hmc::Table table;
+
+    uint32_t* d_areas = nullptr;            // Q counts
+    unsigned long long* d_stats = nullptr;  // 1 + max bins
+    int32_t* d_gbin = nullptr;
+    int32_t stats_bins_cap = 0;
+
+    hmc::Tiling tiling;
+    bool tiling_explicit = false;
+
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
+    int64_t prof_launches = 0, prof_su = 0;
+};
+
+namespace hmc {
+
+// Kernels (defined in their .hip files).
+hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed);
+hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request);
+hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
+hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas
+hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins);
+int lds_limit_bytes();
+
+}  // namespace hmc

@@ -1,0 +1,199 @@
+// init_stats.hip -- initial microstructure and grain statistics.
+//
+// Voronoi labelling: the paper does not state its initial polycrystal; the
+// library uses a seeded Voronoi tessellation (point g from Philox with
+// counter (g, 0, 0, 0x564F524E), fixed-point coordinates in 1/256 site,
+// periodic squared distance in integers, ties to the lower index).  Points
+// are generated on the host and staged through LDS; each thread labels one
+// site by exact brute force.
+//
+// Grain statistics: the orientation distribution the paper follows over time
+// (Sec. 5) is the area fraction of grains grouped by orientation class.
+// A histogram kernel counts sites per spin value with run-length
+// aggregation inside each wavefront (neighbouring sites of a row mostly share
+// a grain, so one atomic per run instead of one per site); a second kernel
+// reduces per-grain areas into the present-grain count (wavefront ballot +
+// popcount) and per-bin areas (LDS-privatised bins).
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace hmc {
+
+namespace {
+
+constexpr int kVorThreads = 256;
+constexpr int kVorChunk = 1024;
+
+template <typename Dist, typename Spin>
+__global__ void __launch_bounds__(kVorThreads)
+voronoi_kernel(Spin* __restrict__ out, const int32_t* __restrict__ pts, int32_t G, uint32_t Lx, uint32_t Ly,
+               uint32_t Lz, int ndim, uint64_t N) {
+    __shared__ int32_t sp[kVorChunk * 3];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < N;
+    const int32_t x = (int32_t)(i % Lx), y = (int32_t)((i / Lx) % Ly), z = (int32_t)(i / ((uint64_t)Lx * Ly));
+    const int32_t pos[3] = {256 * x, 256 * y, 256 * z};
+    const int32_t span[3] = {(int32_t)(256 * Lx), (int32_t)(256 * Ly), (int32_t)(256 * Lz)};
+    Dist best = ~(Dist)0;
+    int32_t bg = 0;
+    for (int32_t g0 = 0; g0 < G; g0 += kVorChunk) {
+        const int32_t n = min(kVorChunk, G - g0);
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < n * 3; k += blockDim.x) sp[k] = pts[(size_t)g0 * 3 + k];
+        __syncthreads();
+        if (active) {
+            for (int32_t g = 0; g < n; ++g) {
+                Dist d2 = 0;
+                for (int a = 0; a < ndim; ++a) {
+                    int32_t dd = sp[3 * g + a] - pos[a];
+                    dd = dd < 0 ? -dd : dd;
+                    dd = min(dd, span[a] - dd);
+                    d2 += (Dist)dd * (Dist)dd;
+                }
+                if (d2 < best) {   // ascending g: ties keep the lower index
+                    best = d2;
+                    bg = g0 + g;
+                }
+            }
+        }
+    }
+    if (active) out[i] = (Spin)bg;
+}
+
+constexpr int kHistThreads = 256;
+
+template <typename Spin>
+__global__ void __launch_bounds__(kHistThreads)
+histogram_kernel(const Spin* __restrict__ s, uint64_t N, uint32_t* __restrict__ areas) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // uniform trip count per wave so that the wave-level votes see all lanes
+    const uint64_t wave_base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (uint64_t b = wave_base; b < N; b += stride) {
+        const uint64_t i = b + lane;
+        const bool ok = i < N;
+        const int32_t q = ok ? (int32_t)s[i] : -1;
+        const int32_t prev = __shfl_up(q, 1);
+        const bool head = ok && (lane == 0 || prev != q);
+        const uint64_t heads = __ballot(head);
+        const uint64_t valid = __ballot(ok);
+        if (head) {
+            // run ends at the next head or at the last valid lane
+            const uint64_t later = heads & ~((2ull << lane) - 1ull);
+            const uint32_t end = later ? (uint32_t)__ffsll((long long)later) - 1u
+                                       : 64u - (uint32_t)__clzll((long long)valid);
+            atomicAdd(&areas[q], end - lane);
+        }
+    }
+}
+
+constexpr int kBinThreads = 256;
+constexpr int kMaxLdsBins = 4096;
+
+__global__ void __launch_bounds__(kBinThreads)
+bin_stats_kernel(const uint32_t* __restrict__ areas, int32_t Q, const int32_t* __restrict__ gbin, int32_t n_bins,
+                 unsigned long long* __restrict__ out /* 1 + n_bins */) {
+    __shared__ unsigned long long bins[kMaxLdsBins];
+    const bool lds_bins = n_bins <= kMaxLdsBins;
+    if (lds_bins)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x) bins[b] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t wave_base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (int64_t b0 = wave_base; b0 < Q; b0 += stride) {
+        const int64_t q = b0 + lane;
+        const uint32_t a = q < Q ? areas[q] : 0u;
+        const uint64_t present = __ballot(a > 0);
+        if (lane == 0 && present) atomicAdd(&out[0], (unsigned long long)__popcll(present));
+        if (a > 0 && gbin != nullptr) {
+            const int32_t bin = gbin[q];
+            if (bin >= 0 && bin < n_bins) {
+                if (lds_bins) atomicAdd(&bins[bin], (unsigned long long)a);
+                else atomicAdd(&out[1 + bin], (unsigned long long)a);
+            }
+        }
+    }
+    __syncthreads();
+    if (lds_bins)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+            if (bins[b]) atomicAdd(&out[1 + b], bins[b]);
+}
+
+int grid_for(uint64_t n, int threads, int cap) {
+    uint64_t g = (n + threads - 1) / threads;
+    if (g > (uint64_t)cap) g = cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+}  // namespace
+
+hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed) {
+    const int32_t G = L->Q;
+    const int ndim = L->ndim;
+    std::vector<int32_t> pts((size_t)G * 3, 0);
+    const uint32_t k0 = (uint32_t)(vseed & 0xFFFFFFFFu), k1 = (uint32_t)(vseed >> 32);
+    for (int32_t g = 0; g < G; ++g) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)g, 0u, 0u, 0x564F524Eu, k0, k1, r);
+        for (int a = 0; a < ndim; ++a)
+            pts[(size_t)g * 3 + a] = (int32_t)(((uint64_t)r[a] * ((uint64_t)L->desc.dims[a] * 256u)) >> 32);
+    }
+    void* dpts = nullptr;
+    const size_t bytes = pts.size() * sizeof(int32_t);
+    HMC_TRY(dev_alloc(&dpts, bytes, "voronoi points"));
+    hipError_t e = hipMemcpyAsync(dpts, pts.data(), bytes, hipMemcpyHostToDevice, L->stream);
+    const uint32_t Lx = (uint32_t)L->desc.dims[0], Ly = (uint32_t)L->desc.dims[1];
+    const uint32_t Lz = ndim == 3 ? (uint32_t)L->desc.dims[2] : 1u;
+    // 32-bit distances suffice while ndim * (128 * L_max)^2 < 2^32
+    uint64_t half = 128ull * std::max(Lx, std::max(Ly, Lz));
+    const bool d32 = (uint64_t)ndim * half * half < (1ull << 32);
+    const uint64_t N = (uint64_t)L->N;
+    const dim3 grid((unsigned)((N + kVorThreads - 1) / kVorThreads));
+    if (e == hipSuccess) {
+        void* out = L->spins[L->cur];
+        if (L->desc.spin == HMC_I16) {
+            if (d32) voronoi_kernel<uint32_t, int16_t><<<grid, kVorThreads, 0, L->stream>>>(
+                         (int16_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+            else voronoi_kernel<uint64_t, int16_t><<<grid, kVorThreads, 0, L->stream>>>(
+                     (int16_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+        } else {
+            if (d32) voronoi_kernel<uint32_t, int32_t><<<grid, kVorThreads, 0, L->stream>>>(
+                         (int32_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+            else voronoi_kernel<uint64_t, int32_t><<<grid, kVorThreads, 0, L->stream>>>(
+                     (int32_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    dev_free(dpts, bytes);
+    if (e != hipSuccess) return hip_fail(e, "voronoi");
+    return HMC_OK;
+}
+
+hmc_status launch_histogram(hmc_lattice* L) {
+    HMC_HIP(hipMemsetAsync(L->d_areas, 0, (size_t)L->Q * sizeof(uint32_t), L->stream));
+    const uint64_t N = (uint64_t)L->N;
+    const int grid = grid_for(N, kHistThreads, 4096);
+    if (L->desc.spin == HMC_I16)
+        histogram_kernel<int16_t><<<grid, kHistThreads, 0, L->stream>>>((const int16_t*)L->spins[L->cur], N,
+                                                                          L->d_areas);
+    else
+        histogram_kernel<int32_t><<<grid, kHistThreads, 0, L->stream>>>((const int32_t*)L->spins[L->cur], N,
+                                                                          L->d_areas);
+    HMC_HIP(hipGetLastError());
+    return HMC_OK;
+}
+
+hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins) {
+    HMC_HIP(hipMemsetAsync(L->d_stats, 0, (size_t)(1 + n_bins) * sizeof(unsigned long long), L->stream));
+    const int grid = grid_for((uint64_t)L->Q, kBinThreads, 1024);
+    bin_stats_kernel<<<grid, kBinThreads, 0, L->stream>>>(L->d_areas, L->Q, d_gbin, n_bins, L->d_stats);
+    HMC_HIP(hipGetLastError());
+    return HMC_OK;
+}
+
+}  // namespace hmc

@@ -1,0 +1,486 @@
+// runtime.hip -- host runtime and C ABI of libhmc.
+//
+// Validation happens here, on the host, before any device work: invalid
+// arguments return HMC_E_INVAL without touching the GPU.  The threshold
+// table T(d) = min(2^32-1, floor(2^32 exp(-d/(65536 kT)))) of the Metropolis
+// rule (Sec. 3-4 of the paper) is evaluated here in double precision with the
+// C library exp and uploaded; kernels only compare integers.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hmc {
+
+namespace {
+thread_local std::string g_error;
+std::atomic<uint64_t> g_bytes{0};
+
+uint64_t byte_cap() {
+    static uint64_t cap = [] {
+        const char* s = std::getenv("HMC_MAX_BYTES");
+        if (!s || !*s) return std::numeric_limits<uint64_t>::max();
+        return (uint64_t)std::strtoull(s, nullptr, 10);
+    }();
+    return cap;
+}
+
+// Keep libm's exp out of reach of any compile-time rewriting.
+double (*volatile g_exp)(double) = &std::exp;
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+hmc_status fail(hmc_status code, const std::string& msg) {
+    g_error = msg;
+    return code;
+}
+
+hmc_status hip_fail(hipError_t e, const char* what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? HMC_E_NOMEM : HMC_E_DEVICE;
+}
+
+hmc_status dev_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    const uint64_t now = g_bytes.fetch_add(bytes) + bytes;
+    if (now > byte_cap()) {
+        g_bytes.fetch_sub(bytes);
+        return fail(HMC_E_NOMEM, std::string(what) + ": HMC_MAX_BYTES cap exceeded");
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        g_bytes.fetch_sub(bytes);
+        *p = nullptr;
+        return hip_fail(e, what);
+    }
+    return HMC_OK;
+}
+
+void dev_free(void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    g_bytes.fetch_sub(bytes == 0 ? 16 : bytes);
+}
+
+NbrInfo nbr_info(int nbr) {
+    switch (nbr) {
+    case HMC_VN4: return {4, 2, 2};
+    case HMC_MOORE8: return {8, 4, 2};
+    case HMC_VN6: return {6, 2, 3};
+    case HMC_MOORE26: return {26, 8, 3};
+    default: return {0, 0, 0};
+    }
+}
+
+uint32_t threshold_value(int64_t d, float kT) {
+    const double x = (double)d / (65536.0 * (double)kT);
+    const double v = std::ldexp(g_exp(-x), 32);
+    if (v >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)std::floor(v);
+}
+
+namespace {
+constexpr size_t kTableCapBytes = 256ull << 20;
+}
+
+hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax, hipStream_t stream) {
+    uint32_t bits;
+    std::memcpy(&bits, &kT, sizeof bits);
+    if (tab.valid && tab.kT_bits == bits && tab.Bmin == Bmin && tab.Bmax == Bmax) return HMC_OK;
+    const int64_t R = (int64_t)Bmax - Bmin;
+    int64_t dn_lo = -M;
+    while (dn_lo <= M && (int64_t)J_fx * dn_lo + R <= 0) ++dn_lo;
+    if (dn_lo > M) dn_lo = M;   // no positive d possible; keep one row
+    const int64_t rows = M - dn_lo + 1;
+    const int64_t TW = 2 * R + 1;
+    const size_t bytes = (size_t)(rows * TW) * sizeof(uint32_t);
+    if (bytes > kTableCapBytes)
+        return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
+    std::vector<uint32_t> host((size_t)(rows * TW), 0xFFFFFFFFu);
+    for (int64_t r = 0; r < rows; ++r) {
+        const int64_t dn = dn_lo + r;
+        for (int64_t j = 0; j < TW; ++j) {
+            const int64_t d = (int64_t)J_fx * dn + (j - R);
+            if (d > 0) host[(size_t)(r * TW + j)] = threshold_value(d, kT);
+        }
+    }
+    if (tab.bytes < bytes) {
+        free_table(tab);
+        void* p = nullptr;
+        HMC_TRY(dev_alloc(&p, bytes, "threshold table"));
+        tab.dev = static_cast<uint32_t*>(p);
+        tab.bytes = bytes;
+    }
+    HMC_HIP(hipMemcpyAsync(tab.dev, host.data(), bytes, hipMemcpyHostToDevice, stream));
+    HMC_HIP(hipStreamSynchronize(stream));
+    tab.dn_lo = (int32_t)dn_lo;
+    tab.rows = (int32_t)rows;
+    tab.R = (int32_t)R;
+    tab.TW = (int32_t)TW;
+    tab.kT_bits = bits;
+    tab.Bmin = Bmin;
+    tab.Bmax = Bmax;
+    tab.valid = true;
+    return HMC_OK;
+}
+
+void free_table(Table& tab) {
+    dev_free(tab.dev, tab.bytes);
+    tab = Table{};
+}
+
+namespace {
+
+hmc_status validate_desc(const hmc_lattice_desc* d, int32_t n_grains) {
+    if (!d) return fail(HMC_E_INVAL, "desc is NULL");
+    const NbrInfo ni = nbr_info(d->nbr);
+    if (ni.M == 0) return fail(HMC_E_INVAL, "unknown neighbourhood " + std::to_string(d->nbr));
+    if (d->ndim != ni.ndim)
+        return fail(HMC_E_INVAL, "neighbourhood " + std::to_string(d->nbr) + " needs ndim " + std::to_string(ni.ndim));
+    uint64_t N = 1;
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->dims[a] < 4 || d->dims[a] % 2 != 0 || d->dims[a] > (1 << 22))
+            return fail(HMC_E_INVAL, "lattice side " + std::to_string(d->dims[a]) + " must be even and in [4, 2^22]");
+        N *= (uint64_t)d->dims[a];
+    }
+    if (N >= (1ull << 32)) return fail(HMC_E_INVAL, "lattice must have fewer than 2^32 sites");
+    if (d->spin != HMC_I16 && d->spin != HMC_I32) return fail(HMC_E_INVAL, "spin type must be HMC_I16 or HMC_I32");
+    if (d->proposal != HMC_PROP_NEIGHBOUR && d->proposal != HMC_PROP_UNIFORM)
+        return fail(HMC_E_INVAL, "unknown trial mode");
+    if (d->J_fx < 1 || d->J_fx > (1 << 24)) return fail(HMC_E_INVAL, "J_fx must be in [1, 2^24]");
+    if (n_grains < 1) return fail(HMC_E_INVAL, "n_grains must be >= 1");
+    if (d->spin == HMC_I16 && n_grains > 32767) return fail(HMC_E_INVAL, "n_grains > 32767 needs int32 spins");
+    if ((int64_t)d->J_fx * ni.M >= (1ll << 31)) return fail(HMC_E_RANGE, "J_fx * M overflows int32");
+    return HMC_OK;
+}
+
+hmc_status check_energy_range(const hmc_lattice* L, int32_t Bmin, int32_t Bmax) {
+    const int64_t maxabs = std::max<int64_t>(std::llabs((int64_t)Bmin), std::llabs((int64_t)Bmax));
+    if ((int64_t)L->desc.J_fx * L->M + 2 * maxabs >= (1ll << 31))
+        return fail(HMC_E_RANGE, "J_fx*M + 2 max|B| must stay below 2^31");
+    return HMC_OK;
+}
+
+void destroy(hmc_lattice* L) {
+    if (!L) return;
+    if (L->stream) (void)hipStreamSynchronize(L->stream);
+    const size_t sb = (size_t)L->N * L->spin_bytes;
+    dev_free(L->spins[0], sb);
+    dev_free(L->spins[1], sb);
+    dev_free(L->snap, sb);
+    dev_free(L->dB, (size_t)L->Q * 4);
+    dev_free(L->d_areas, (size_t)L->Q * 4);
+    dev_free(L->d_stats, (size_t)(1 + L->stats_bins_cap) * 8);
+    dev_free(L->d_gbin, (size_t)L->Q * 4);
+    free_table(L->table);
+    for (auto& e : L->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+    delete L;
+}
+
+hmc_status create(const hmc_lattice_desc* d, int32_t n_grains, void* stream, hmc_lattice** out) {
+    if (!out) return fail(HMC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    HMC_TRY(validate_desc(d, n_grains));
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(HMC_E_DEVICE, "no HIP device available");
+    hmc_lattice* L = new hmc_lattice();
+    L->desc = *d;
+    if (d->ndim == 2) L->desc.dims[2] = 1;
+    L->Q = n_grains;
+    const NbrInfo ni = nbr_info(d->nbr);
+    L->M = ni.M;
+    L->C = ni.C;
+    L->ndim = ni.ndim;
+    L->N = (int64_t)L->desc.dims[0] * L->desc.dims[1] * L->desc.dims[2];
+    L->spin_bytes = d->spin == HMC_I16 ? 2 : 4;
+    (void)hipGetDevice(&L->device);
+    hmc_status st = HMC_OK;
+    hipError_t e;
+    if (stream) {
+        L->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { st = hip_fail(e, "hipStreamCreate"); L->stream = nullptr; }
+        L->own_stream = true;
+    }
+    const size_t sb = (size_t)L->N * L->spin_bytes;
+    if (st == HMC_OK) st = dev_alloc(&L->spins[0], sb, "spins");
+    if (st == HMC_OK) st = dev_alloc(&L->spins[1], sb, "spins (second buffer)");
+    if (st == HMC_OK) st = dev_alloc(reinterpret_cast<void**>(&L->dB), (size_t)L->Q * 4, "grain energies");
+    if (st == HMC_OK) st = dev_alloc(reinterpret_cast<void**>(&L->d_areas), (size_t)L->Q * 4, "grain areas");
+    if (st == HMC_OK) st = dev_alloc(reinterpret_cast<void**>(&L->d_gbin), (size_t)L->Q * 4, "grain bins");
+    if (st == HMC_OK) {
+        L->stats_bins_cap = 64;
+        st = dev_alloc(reinterpret_cast<void**>(&L->d_stats), (size_t)(1 + L->stats_bins_cap) * 8, "stats");
+    }
+    if (st == HMC_OK) {
+        e = hipMemsetAsync(L->spins[0], 0, sb, L->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(L->dB, 0, (size_t)L->Q * 4, L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) st = hip_fail(e, "lattice set-up");
+    }
+    if (st != HMC_OK) {
+        destroy(L);
+        return st;
+    }
+    L->hB.assign((size_t)L->Q, 0);
+    L->Bmin = L->Bmax = 0;
+    *out = L;
+    return HMC_OK;
+}
+
+}  // namespace
+}  // namespace hmc
+
+using namespace hmc;
+
+extern "C" {
+
+int32_t hmc_abi_version(void) { return 1; }
+
+const char* hmc_last_error(void) { return g_error.c_str(); }
+
+int32_t hmc_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+hmc_status hmc_lattice_create(const hmc_lattice_desc* desc, int32_t n_grains, void* stream, hmc_lattice** out) {
+    g_error.clear();
+    return create(desc, n_grains, stream, out);
+}
+
+hmc_status hmc_lattice_init(const hmc_lattice_desc* desc, int32_t n_grains, uint64_t voronoi_seed, void* stream,
+                            hmc_lattice** out) {
+    g_error.clear();
+    hmc_lattice* L = nullptr;
+    HMC_TRY(create(desc, n_grains, stream, &L));
+    const hmc_status st = launch_voronoi(L, voronoi_seed);
+    if (st != HMC_OK) {
+        destroy(L);
+        *out = nullptr;
+        return st;
+    }
+    *out = L;
+    return HMC_OK;
+}
+
+hmc_status hmc_lattice_free(hmc_lattice* L) {
+    g_error.clear();
+    destroy(L);
+    return HMC_OK;
+}
+
+hmc_status hmc_set_grain_energy(hmc_lattice* L, const int32_t* B_fx, int32_t n_grains, int32_t on_device) {
+    g_error.clear();
+    if (!L || !B_fx) return fail(HMC_E_INVAL, "NULL argument");
+    if (n_grains != L->Q)
+        return fail(HMC_E_INVAL, "n_grains " + std::to_string(n_grains) + " != lattice Q " + std::to_string(L->Q));
+    std::vector<int32_t> h((size_t)n_grains);
+    if (on_device) {
+        HMC_HIP(hipMemcpyAsync(h.data(), B_fx, (size_t)n_grains * 4, hipMemcpyDeviceToHost, L->stream));
+        HMC_HIP(hipStreamSynchronize(L->stream));
+    } else {
+        std::memcpy(h.data(), B_fx, (size_t)n_grains * 4);
+    }
+    int32_t lo = h[0], hi = h[0];
+    for (int32_t v : h) {
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+    }
+    HMC_TRY(check_energy_range(L, lo, hi));
+    HMC_HIP(hipMemcpyAsync(L->dB, h.data(), (size_t)n_grains * 4, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    L->hB.swap(h);
+    L->Bmin = lo;
+    L->Bmax = hi;
+    return HMC_OK;
+}
+
+hmc_status hmc_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (!(kT > 0.0f) || !std::isfinite(kT)) return fail(HMC_E_INVAL, "kT must be positive and finite");
+    if (n_mcs < 0) return fail(HMC_E_INVAL, "n_mcs must be >= 0");
+    return launch_sweep(L, kT, n_mcs, seed);
+}
+
+hmc_status hmc_grain_areas(hmc_lattice* L, int64_t* areas_out) {
+    g_error.clear();
+    if (!L || !areas_out) return fail(HMC_E_INVAL, "NULL argument");
+    HMC_TRY(launch_histogram(L));
+    std::vector<uint32_t> a((size_t)L->Q);
+    HMC_HIP(hipMemcpyAsync(a.data(), L->d_areas, a.size() * 4, hipMemcpyDeviceToHost, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    for (size_t q = 0; q < a.size(); ++q) areas_out[q] = (int64_t)a[q];
+    return HMC_OK;
+}
+
+hmc_status hmc_texture_stats(hmc_lattice* L, const int32_t* grain_bin, int32_t n_bins, int32_t* n_grains_out,
+                             double* mean_area_out, double* frac_out) {
+    g_error.clear();
+    if (!L || !n_grains_out || !mean_area_out) return fail(HMC_E_INVAL, "NULL argument");
+    if (n_bins < 0 || n_bins > (1 << 20)) return fail(HMC_E_INVAL, "n_bins must be in [0, 2^20]");
+    if (n_bins > 0 && (!grain_bin || !frac_out)) return fail(HMC_E_INVAL, "grain_bin / frac_out is NULL");
+    if (grain_bin && n_bins > 0)
+        for (int32_t q = 0; q < L->Q; ++q)
+            if (grain_bin[q] < -1 || grain_bin[q] >= n_bins)
+                return fail(HMC_E_INVAL, "grain_bin[" + std::to_string(q) + "] outside [-1, n_bins)");
+    if (n_bins > L->stats_bins_cap) {
+        dev_free(L->d_stats, (size_t)(1 + L->stats_bins_cap) * 8);
+        L->d_stats = nullptr;
+        L->stats_bins_cap = 0;
+        HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_stats), (size_t)(1 + n_bins) * 8, "stats"));
+        L->stats_bins_cap = n_bins;
+    }
+    const int32_t* dgb = nullptr;
+    if (grain_bin && n_bins > 0) {
+        HMC_HIP(hipMemcpyAsync(L->d_gbin, grain_bin, (size_t)L->Q * 4, hipMemcpyHostToDevice, L->stream));
+        dgb = L->d_gbin;
+    }
+    HMC_TRY(launch_histogram(L));
+    HMC_TRY(launch_bin_stats(L, dgb, n_bins));
+    std::vector<unsigned long long> h((size_t)(1 + n_bins));
+    HMC_HIP(hipMemcpyAsync(h.data(), L->d_stats, h.size() * 8, hipMemcpyDeviceToHost, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    const int64_t ng = (int64_t)h[0];
+    *n_grains_out = (int32_t)ng;
+    *mean_area_out = ng > 0 ? (double)L->N / (double)ng : 0.0;
+    for (int32_t b = 0; b < n_bins; ++b) frac_out[b] = (double)h[1 + b] / (double)L->N;
+    return HMC_OK;
+}
+
+hmc_status hmc_get_spins(hmc_lattice* L, void* host_dst, uint64_t bytes) {
+    g_error.clear();
+    if (!L || !host_dst) return fail(HMC_E_INVAL, "NULL argument");
+    if (bytes != (uint64_t)L->N * L->spin_bytes) return fail(HMC_E_INVAL, "bytes must equal N * spin size");
+    HMC_HIP(hipMemcpyAsync(host_dst, L->spins[L->cur], bytes, hipMemcpyDeviceToHost, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_set_spins(hmc_lattice* L, const void* host_src, uint64_t bytes) {
+    g_error.clear();
+    if (!L || !host_src) return fail(HMC_E_INVAL, "NULL argument");
+    if (bytes != (uint64_t)L->N * L->spin_bytes) return fail(HMC_E_INVAL, "bytes must equal N * spin size");
+    for (int64_t i = 0; i < L->N; ++i) {
+        const int64_t v = L->spin_bytes == 2 ? (int64_t) static_cast<const int16_t*>(host_src)[i]
+                                             : (int64_t) static_cast<const int32_t*>(host_src)[i];
+        if (v < 0 || v >= L->Q)
+            return fail(HMC_E_INVAL, "spin " + std::to_string(v) + " at site " + std::to_string(i) + " outside [0, Q)");
+    }
+    HMC_HIP(hipMemcpyAsync(L->spins[L->cur], host_src, bytes, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_snapshot(hmc_lattice* L) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    const size_t sb = (size_t)L->N * L->spin_bytes;
+    if (!L->snap) HMC_TRY(dev_alloc(&L->snap, sb, "snapshot"));
+    HMC_HIP(hipMemcpyAsync(L->snap, L->spins[L->cur], sb, hipMemcpyDeviceToDevice, L->stream));
+    L->snap_mcs = L->mcs;
+    L->has_snap = true;
+    return HMC_OK;
+}
+
+hmc_status hmc_restore(hmc_lattice* L) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (!L->has_snap) return fail(HMC_E_STATE, "no snapshot taken");
+    const size_t sb = (size_t)L->N * L->spin_bytes;
+    HMC_HIP(hipMemcpyAsync(L->spins[L->cur], L->snap, sb, hipMemcpyDeviceToDevice, L->stream));
+    L->mcs = L->snap_mcs;
+    return HMC_OK;
+}
+
+hmc_status hmc_get_mcs(const hmc_lattice* L, uint64_t* mcs) {
+    g_error.clear();
+    if (!L || !mcs) return fail(HMC_E_INVAL, "NULL argument");
+    *mcs = L->mcs;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_mcs(hmc_lattice* L, uint64_t mcs) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    L->mcs = mcs;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_tiling(hmc_lattice* L, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (tx < 0 || ty < 0 || tz < 0 || mcs_per_launch < 0) return fail(HMC_E_INVAL, "tiling values must be >= 0");
+    Tiling t;
+    t.tx = tx;
+    t.ty = ty;
+    t.tz = L->ndim == 3 ? tz : 1;
+    t.k = mcs_per_launch;
+    HMC_TRY(choose_tiling(L, t, true));
+    L->tiling = t;
+    L->tiling_explicit = true;
+    return HMC_OK;
+}
+
+hmc_status hmc_get_tiling(const hmc_lattice* L, int32_t* out4) {
+    g_error.clear();
+    if (!L || !out4) return fail(HMC_E_INVAL, "NULL argument");
+    Tiling t = L->tiling;
+    HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
+    out4[0] = t.tx;
+    out4[1] = t.ty;
+    out4[2] = t.tz;
+    out4[3] = t.k;
+    return HMC_OK;
+}
+
+hmc_status hmc_profile(hmc_lattice* L, int32_t enable) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    L->profiling = enable != 0;
+    return HMC_OK;
+}
+
+hmc_status hmc_profile_read(hmc_lattice* L, double* kernel_ms, int64_t* launches, int64_t* site_updates) {
+    g_error.clear();
+    if (!L || !kernel_ms || !launches || !site_updates) return fail(HMC_E_INVAL, "NULL argument");
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    double total = 0.0;
+    for (size_t i = 0; i < L->events_used; ++i) {
+        float ms = 0.0f;
+        HMC_HIP(hipEventElapsedTime(&ms, L->events[i].first, L->events[i].second));
+        total += ms;
+    }
+    *kernel_ms = total;
+    *launches = L->prof_launches;
+    *site_updates = L->prof_su;
+    L->events_used = 0;
+    L->prof_launches = 0;
+    L->prof_su = 0;
+    return HMC_OK;
+}
+
+hmc_status hmc_synchronize(hmc_lattice* L) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    return HMC_OK;
+}
+
+}  // extern "C"
