@@ -102,16 +102,21 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     if (dn_lo > M) dn_lo = M;   // no positive d possible; keep one row
     const int64_t rows = M - dn_lo + 1;
     const int64_t TW = 2 * R + 1;
-    const size_t bytes = (size_t)(rows * TW) * sizeof(uint32_t);
+    const size_t entries = (size_t)(rows * TW);
+    const size_t bytes = (entries + 2 * (size_t)rows) * sizeof(uint32_t);
     if (bytes > kTableCapBytes)
         return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
-    std::vector<uint32_t> host((size_t)(rows * TW), 0xFFFFFFFFu);
+    std::vector<uint32_t> host(entries + 2 * (size_t)rows, 0xFFFFFFFFu);
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t dn = dn_lo + r;
         for (int64_t j = 0; j < TW; ++j) {
             const int64_t d = (int64_t)J_fx * dn + (j - R);
             if (d > 0) host[(size_t)(r * TW + j)] = threshold_value(d, kT);
         }
+        const int64_t dmax = (int64_t)J_fx * dn + R;
+        const int64_t dmin = std::max<int64_t>(1, (int64_t)J_fx * dn - R);
+        host[entries + 2 * r] = dmax > 0 ? threshold_value(dmax, kT) : 0xFFFFFFFFu;
+        host[entries + 2 * r + 1] = dmax > 0 ? threshold_value(dmin, kT) : 0xFFFFFFFFu;
     }
     if (tab.bytes < bytes) {
         free_table(tab);
@@ -120,6 +125,7 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
         tab.dev = static_cast<uint32_t*>(p);
         tab.bytes = bytes;
     }
+    tab.bounds = tab.dev + entries;
     HMC_HIP(hipMemcpyAsync(tab.dev, host.data(), bytes, hipMemcpyHostToDevice, stream));
     HMC_HIP(hipStreamSynchronize(stream));
     tab.dn_lo = (int32_t)dn_lo;

@@ -29,6 +29,7 @@
 //     sites, so SIMD lanes are not wasted on interior sites.
 //   * Acceptance is integer: d = J_fx*(c(q)-c(q')) + B[q'] - B[q], accept iff
 //     d <= 0 or r1 < T(d) from the host-built uint32 table.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,14 +42,19 @@ namespace hmc {
 
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 1024;
 constexpr int kWave = 64;
+constexpr int kMaxRows = 64;        // threshold rows: at most 2M+1 = 53
+constexpr int kMaxPasses = 64;      // colour passes fused in one launch
+constexpr int kLdsGrainLimit = 4096; // grain energies staged in LDS up to this Q
+constexpr int kStaticLds = 8 + 8 * kMaxRows + 64;   // qcount + tbound + slack
 
 struct SweepParams {
     const void* src;
     void* dst;
     const int32_t* B;
     const uint32_t* T;
+    const uint32_t* Tb;       // per-row (lower, upper) bounds of T
     uint32_t Lx, Ly, Lz;
     uint32_t TX, TY, TZ;
     uint32_t ntx, nty, ntz;
@@ -59,10 +65,12 @@ struct SweepParams {
     uint32_t k0, k1;          // Philox key
     int32_t J_fx;
     int32_t Q;
-    int32_t dn_lo, TW, R;     // threshold-table layout
+    int32_t dn_lo, TW, R, rows;   // threshold-table layout
     uint32_t uniform;         // 1: symmetric trial spins
     uint32_t xcd_group;       // tiles per XCD (0: identity mapping)
-    uint32_t queue_off, coord_off;   // byte offsets in dynamic LDS
+    uint32_t queue_off, coord_off, grain_off;   // byte offsets in dynamic LDS
+    uint32_t m_bx, m_by, m_tx, m_ty;            // reciprocals (see magic())
+    uint32_t m_pass[kMaxPasses][2];             // per pass: per-row and rows reciprocals
 };
 
 template <int NBR>
@@ -89,26 +97,29 @@ __device__ __forceinline__ uint32_t wrap_coord(int64_t a, uint32_t L) {
     return (uint32_t)(r < 0 ? r + L : r);
 }
 
-// floor(f / d) for f * d < 2^32 via a 32-bit reciprocal (d >= 1).
-struct FastDiv {
-    uint32_t d, m;
-    __device__ __forceinline__ explicit FastDiv(uint32_t d_) : d(d_), m(d_ > 1 ? (uint32_t)(0x100000000ull / d_) + 1u : 0u) {}
-    __device__ __forceinline__ uint32_t div(uint32_t f) const { return d > 1 ? __umulhi(f, m) : f; }
-};
+// floor(f / d) = umulhi(f, m) with m = floor(2^32 / d) + 1, exact whenever
+// f * d < 2^32 (all box indices here are < 2^16 and d < 2^10); d = 1 is
+// encoded as m = 0.  The reciprocals are computed on the host.
+__host__ __device__ inline uint32_t magic(uint32_t d) { return d > 1 ? (uint32_t)(0x100000000ull / d) + 1u : 0u; }
+__device__ __forceinline__ uint32_t fdiv(uint32_t f, uint32_t m) { return m ? __umulhi(f, m) : f; }
 
-template <int NBR, typename Spin>
+template <int NBR, typename Spin, bool kGrainsInLds>
 __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
-    using T = Traits<NBR>;
-    constexpr int M = T::M, C = T::C, D = T::D;
+    using Tr = Traits<NBR>;
+    constexpr int M = Tr::M, C = Tr::C, D = Tr::D;
     constexpr bool kCheckerboard = (NBR == HMC_VN4 || NBR == HMC_VN6);
+    constexpr int kUnroll = 4;
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t qcount[2];
+    __shared__ uint32_t tbound[2 * kMaxRows];
     Spin* box = reinterpret_cast<Spin*>(smem);
     uint32_t* queue = reinterpret_cast<uint32_t*>(smem + p.queue_off);
     uint32_t* gxs = reinterpret_cast<uint32_t*>(smem + p.coord_off);
     uint32_t* gys = gxs + p.BX;
     uint32_t* gzs = gys + p.BY;
+    int32_t* sB = reinterpret_cast<int32_t*>(smem + p.grain_off);
+    const int32_t* __restrict__ Bq = kGrainsInLds ? sB : p.B;
 
     const Spin* __restrict__ src = static_cast<const Spin*>(p.src);
     Spin* __restrict__ dst = static_cast<Spin*>(p.dst);
@@ -116,7 +127,6 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
-    const uint32_t nwaves = blockDim.x / kWave;
     const uint32_t nthr = blockDim.x;
 
     // Tile of this workgroup.  Consecutive workgroups are spread over the 8
@@ -127,25 +137,42 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
     const uint32_t tx = b % p.ntx;
     const uint32_t ty = (b / p.ntx) % p.nty;
     const uint32_t tz = b / (p.ntx * p.nty);
-    const int64_t H = p.H;
-    const int64_t Hz = (D == 3) ? H : 0;
-    const int64_t x0 = (int64_t)tx * p.TX - H;
-    const int64_t y0 = (int64_t)ty * p.TY - H;
-    const int64_t z0 = (int64_t)tz * p.TZ - Hz;
+    const uint32_t H = p.H;
+    const uint32_t Hz = (D == 3) ? H : 0u;
+    const int64_t x0 = (int64_t)tx * p.TX - (int64_t)H;
+    const int64_t y0 = (int64_t)ty * p.TY - (int64_t)H;
+    const int64_t z0 = (int64_t)tz * p.TZ - (int64_t)Hz;
 
     for (uint32_t u = tid; u < p.BX; u += nthr) gxs[u] = wrap_coord(x0 + u, p.Lx);
     for (uint32_t v = tid; v < p.BY; v += nthr) gys[v] = wrap_coord(y0 + v, p.Ly);
     for (uint32_t w = tid; w < p.BZ; w += nthr) gzs[w] = (D == 3) ? wrap_coord(z0 + w, p.Lz) : 0u;
+    for (uint32_t r = tid; r < 2u * (uint32_t)p.rows; r += nthr) tbound[r] = p.Tb[r];
+    if (kGrainsInLds)
+        for (uint32_t q = tid; q < (uint32_t)p.Q; q += nthr) sB[q] = p.B[q];
     if (tid < 2) qcount[tid] = 0;
     __syncthreads();
 
-    // Stage tile + halo: one wave per box row, lanes along x (coalesced).
-    const uint32_t nrows = p.BY * p.BZ;
-    for (uint32_t r = wave; r < nrows; r += nwaves) {
-        const uint32_t v = r % p.BY, w = r / p.BY;
-        const size_t rowbase = (size_t)p.Lx * ((size_t)gys[v] + (size_t)p.Ly * gzs[w]);
-        Spin* brow = box + (size_t)r * p.BX;
-        for (uint32_t u = lane; u < p.BX; u += kWave) brow[u] = src[rowbase + gxs[u]];
+    // Stage tile + halo: flat box index, consecutive threads on consecutive x
+    // (coalesced), kUnroll independent loads in flight per thread.
+    const uint32_t box_n = p.BX * p.BY * p.BZ;
+    for (uint32_t e0 = tid; e0 < box_n; e0 += kUnroll * nthr) {
+        int32_t v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const uint32_t e = e0 + j * nthr;
+            const uint32_t ec = e < box_n ? e : 0u;
+            const uint32_t r = fdiv(ec, p.m_bx);
+            const uint32_t u = ec - __umul24(r, p.BX);
+            const uint32_t w = (D == 3) ? fdiv(r, p.m_by) : 0u;
+            const uint32_t vv = r - __umul24(w, p.BY);
+            const uint32_t g = gxs[u] + p.Lx * (gys[vv] + p.Ly * gzs[w]);
+            v[j] = (int32_t)src[g];
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const uint32_t e = e0 + j * nthr;
+            if (e < box_n) box[e] = (Spin)v[j];
+        }
     }
     __syncthreads();
 
@@ -170,45 +197,53 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
         const uint32_t rows = kCheckerboard ? Wy : Wy / 2;
         const uint32_t planes = (kCheckerboard || D == 2) ? Wz : Wz / 2;
         const uint32_t total = per_row * rows * planes;
-        const FastDiv div_row(per_row), div_rows(rows);
+        const uint32_t m_row = p.m_pass[pass][0], m_rows = p.m_pass[pass][1];
         uint32_t* qc = &qcount[pass & 1];
+        const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = (c >> 2) & 1u;
 
         // ---- phase 1: queue the sites of colour c that can change
-        for (uint32_t f0 = wave * kWave; f0 < total; f0 += nthr) {
-            const uint32_t f = f0 + lane;
-            bool push = false;
-            uint32_t packed = 0;
-            if (f < total) {
-                const uint32_t rr = div_row.div(f);
-                const uint32_t j = f - rr * per_row;
-                const uint32_t pl = div_rows.div(rr);
-                const uint32_t ri = rr - pl * rows;
-                uint32_t u, v, w;
-                if (kCheckerboard) {
-                    v = lo + ri;
-                    w = loz + pl;
-                    const uint32_t a = (lo + v + w + px + py + pz) & 1u;
-                    u = lo + 2 * j + ((c ^ a) & 1u);
-                } else {
-                    const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = (c >> 2) & 1u;
-                    u = lo + 2 * j + ((cx ^ (lo + px)) & 1u);
-                    v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
-                    w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
-                }
-                const uint32_t idx = u + p.BX * (v + p.BY * w);
-                const Spin s = box[idx];
-                bool diff = p.uniform != 0;
+        for (uint32_t f0 = wave * kWave; f0 < total; f0 += 2 * nthr) {
+            bool push[2];
+            uint32_t packed[2];
 #pragma unroll
-                for (int k = 0; k < M; ++k) diff |= (box[(int)idx + off[k]] != s);
-                push = diff;
-                packed = u | (v << 10) | (w << 20);
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t f = f0 + j * nthr + lane;
+                push[j] = false;
+                packed[j] = 0;
+                if (f < total) {
+                    const uint32_t rr = fdiv(f, m_row);
+                    const uint32_t jj = f - __umul24(rr, per_row);
+                    const uint32_t pl = (D == 3) ? fdiv(rr, m_rows) : 0u;
+                    const uint32_t ri = rr - __umul24(pl, rows);
+                    uint32_t u, v, w;
+                    if (kCheckerboard) {
+                        v = lo + ri;
+                        w = loz + pl;
+                        const uint32_t a = (lo + v + w + px + py + pz) & 1u;
+                        u = lo + 2 * jj + ((c ^ a) & 1u);
+                    } else {
+                        u = lo + 2 * jj + ((cx ^ (lo + px)) & 1u);
+                        v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
+                        w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
+                    }
+                    const uint32_t idx = u + __umul24(p.BX, v + __umul24(p.BY, w));
+                    const Spin s = box[idx];
+                    bool diff = p.uniform != 0;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) diff |= (box[(int)idx + off[k]] != s);
+                    push[j] = diff;
+                    packed[j] = u | (v << 10) | (w << 20);
+                }
             }
-            const uint64_t mask = __ballot(push);
-            if (mask) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
-                base = __shfl(base, 0);
-                if (push) queue[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = packed;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint64_t mask = __ballot(push[j]);
+                if (mask) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
+                    base = __shfl(base, 0);
+                    if (push[j]) queue[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = packed[j];
+                }
             }
         }
         __syncthreads();
@@ -216,72 +251,89 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
         // ---- phase 2: Metropolis trial for every queued site
         const uint32_t count = *qc;
         if (tid == 0) qcount[(pass + 1) & 1] = 0;
-        for (uint32_t e = tid; e < count; e += nthr) {
-            const uint32_t packed = queue[e];
-            const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
-            const int idx = (int)(u + p.BX * (v + p.BY * w));
-            const int32_t q = (int32_t)box[idx];
-            const uint32_t site = gxs[u] + p.Lx * (gys[v] + p.Ly * gzs[w]);
-            const Philox2 r = philox_r01(site, t, c, 0u, p.k0, p.k1);
-            int32_t qn;
-            if (!p.uniform) {
-                const uint32_t k = __umulhi(r.r0, (uint32_t)M);
-                int o = off[0];
+        for (uint32_t e0 = tid; e0 < count; e0 += 2 * nthr) {
 #pragma unroll
-                for (int kk = 1; kk < M; ++kk) o = (k == (uint32_t)kk) ? off[kk] : o;
-                qn = (int32_t)box[idx + o];
-            } else {
-                qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(p.Q - 1));
-                if (qn >= p.Q) qn -= p.Q;
-            }
-            if (qn == q) continue;
-            if ((uint32_t)q >= (uint32_t)p.Q || (uint32_t)qn >= (uint32_t)p.Q) continue;
-            int cq = 0, cn = 0;
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t e = e0 + j * nthr;
+                if (e >= count) continue;
+                const uint32_t packed = queue[e];
+                const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
+                const int idx = (int)(u + __umul24(p.BX, v + __umul24(p.BY, w)));
+                const int32_t q = (int32_t)box[idx];
+                if ((uint32_t)q >= (uint32_t)p.Q) continue;
+                const int32_t bq = Bq[q];
+                const uint32_t site = gxs[u] + p.Lx * (gys[v] + p.Ly * gzs[w]);
+                const Philox2 r = philox_r01(site, t, c, 0u, p.k0, p.k1);
+                int32_t qn;
+                if (!p.uniform) {
+                    const uint32_t k = __umulhi(r.r0, (uint32_t)M);
+                    int o = off[0];
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const int32_t s = (int32_t)box[idx + off[k]];
-                cq += (s == q);
-                cn += (s == qn);
+                    for (int kk = 1; kk < M; ++kk) o = (k == (uint32_t)kk) ? off[kk] : o;
+                    qn = (int32_t)box[idx + o];
+                } else {
+                    qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(p.Q - 1));
+                    if (qn >= p.Q) qn -= p.Q;
+                }
+                if (qn == q || (uint32_t)qn >= (uint32_t)p.Q) continue;
+                int cq = 0, cn = 0;
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const int32_t s = (int32_t)box[idx + off[k]];
+                    cq += (s == q);
+                    cn += (s == qn);
+                }
+                const int32_t dn = cq - cn;
+                const int32_t dB = Bq[qn] - bq;
+                const int32_t d = p.J_fx * dn + dB;
+                bool accept = d <= 0;
+                if (!accept) {
+                    // T is non-increasing in d: the row's bounds decide most trials
+                    const int row = dn - p.dn_lo;
+                    if (r.r1 < tbound[2 * row]) accept = true;
+                    else if (r.r1 < tbound[2 * row + 1]) accept = r.r1 < p.T[row * p.TW + dB + p.R];
+                }
+                if (accept) box[idx] = (Spin)qn;
             }
-            const int32_t dn = cq - cn;
-            const int32_t dB = p.B[qn] - p.B[q];
-            const int32_t d = p.J_fx * dn + dB;
-            bool accept = d <= 0;
-            if (!accept) accept = r.r1 < p.T[(dn - p.dn_lo) * p.TW + dB + p.R];
-            if (accept) box[idx] = (Spin)qn;
         }
         __syncthreads();
     }
 
-    // Interior back to global memory.
-    const uint32_t orows = p.TY * p.TZ;
-    for (uint32_t r = wave; r < orows; r += nwaves) {
-        const uint32_t v = (uint32_t)H + r % p.TY, w = (uint32_t)Hz + r / p.TY;
-        const size_t rowbase = (size_t)p.Lx * ((size_t)gys[v] + (size_t)p.Ly * gzs[w]);
-        const Spin* brow = box + (size_t)(v + p.BY * w) * p.BX + H;
-        const uint32_t gx0 = gxs[H];
-        for (uint32_t u = lane; u < p.TX; u += kWave) dst[rowbase + gx0 + u] = brow[u];
+    // Interior back to global memory: flat over the tile, coalesced rows.
+    const uint32_t tile_n = p.TX * p.TY * p.TZ;
+    const uint32_t gx0 = gxs[H];
+    for (uint32_t e = tid; e < tile_n; e += nthr) {
+        const uint32_t r = fdiv(e, p.m_tx);
+        const uint32_t u = e - __umul24(r, p.TX);
+        const uint32_t w = (D == 3) ? fdiv(r, p.m_ty) : 0u;
+        const uint32_t vv = r - __umul24(w, p.TY);
+        const Spin val = box[(H + u) + __umul24(p.BX, (H + vv) + __umul24(p.BY, Hz + w))];
+        dst[gx0 + u + p.Lx * (gys[H + vv] + p.Ly * gzs[Hz + w])] = val;
     }
 }
 
 template <int NBR>
-const void* kernel_for(int spin) {
-    return spin == HMC_I16 ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t>)
-                           : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t>);
+const void* kernel_for(int spin, bool grains_in_lds) {
+    if (spin == HMC_I16)
+        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true>)
+                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false>);
+    return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true>)
+                         : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false>);
 }
 
-const void* kernel_ptr(int nbr, int spin) {
+const void* kernel_ptr(int nbr, int spin, bool grains_in_lds) {
     switch (nbr) {
-    case HMC_VN4: return kernel_for<HMC_VN4>(spin);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8>(spin);
-    case HMC_VN6: return kernel_for<HMC_VN6>(spin);
-    default: return kernel_for<HMC_MOORE26>(spin);
+    case HMC_VN4: return kernel_for<HMC_VN4>(spin, grains_in_lds);
+    case HMC_MOORE8: return kernel_for<HMC_MOORE8>(spin, grains_in_lds);
+    case HMC_VN6: return kernel_for<HMC_VN6>(spin, grains_in_lds);
+    default: return kernel_for<HMC_MOORE26>(spin, grains_in_lds);
     }
 }
 
 struct Layout {
     uint32_t BX, BY, BZ, H;
-    size_t queue_off, coord_off, bytes;
+    size_t queue_off, coord_off, grain_off, bytes;
+    bool grains_in_lds;
 };
 
 Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
@@ -299,7 +351,14 @@ Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
     }
     o.queue_off = (elems * L->spin_bytes + 15) / 16 * 16;
     o.coord_off = o.queue_off + (qcap * 4 + 15) / 16 * 16;
-    o.bytes = o.coord_off + (size_t)(o.BX + o.BY + o.BZ) * 4;
+    o.grain_off = (o.coord_off + (size_t)(o.BX + o.BY + o.BZ) * 4 + 15) / 16 * 16;
+    o.bytes = o.grain_off;
+    o.grains_in_lds = false;
+    const size_t with_grains = o.grain_off + (size_t)L->Q * 4;
+    if (L->Q <= kLdsGrainLimit && (int64_t)with_grains + kStaticLds <= lds_limit_bytes()) {
+        o.grains_in_lds = true;
+        o.bytes = with_grains;
+    }
     return o;
 }
 
@@ -347,12 +406,13 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
             return fail(HMC_E_INVAL, "tile side " + std::to_string(sides[a]) +
                                          " must be an even divisor of the lattice side " + std::to_string(dims[a]));
     }
-    if (r.k < 1 || r.k > 64) return fail(HMC_E_INVAL, "mcs_per_launch must be in [1, 64]");
+    if (r.k < 1 || r.k * L->C > kMaxPasses)
+        return fail(HMC_E_INVAL, "mcs_per_launch * colours must be in [1, " + std::to_string(kMaxPasses) + "]");
     const int passes = r.k * L->C;
     const Layout lay = box_layout(L, r, passes);
     if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
         return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
-    if ((int64_t)lay.bytes + 64 > lds_limit_bytes())
+    if ((int64_t)lay.bytes + kStaticLds > lds_limit_bytes())
         return fail(HMC_E_INVAL, "tile + halo needs " + std::to_string(lay.bytes) + " B of LDS, limit " +
                                      std::to_string(lds_limit_bytes()));
     t = r;
@@ -362,6 +422,7 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
     if (n_mcs == 0) return HMC_OK;
     HMC_TRY(build_table(L->table, kT, L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
+    if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
     Tiling t = L->tiling;
     HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
     L->tiling = t;
@@ -370,6 +431,8 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     SweepParams p{};
     p.B = L->dB;
     p.T = L->table.dev;
+    p.Tb = L->table.bounds;
+    p.rows = L->table.rows;
     p.Lx = (uint32_t)dims[0];
     p.Ly = (uint32_t)dims[1];
     p.Lz = L->ndim == 3 ? (uint32_t)dims[2] : 1u;
@@ -390,7 +453,6 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     const uint32_t ntiles = p.ntx * p.nty * p.ntz;
     p.xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
 
-    const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin);
     int32_t remaining = n_mcs;
     uint64_t t_next = L->mcs;
     while (remaining > 0) {
@@ -403,27 +465,38 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         p.t0 = (uint32_t)t_next;
         p.queue_off = (uint32_t)lay.queue_off;
         p.coord_off = (uint32_t)lay.coord_off;
+        p.grain_off = (uint32_t)lay.grain_off;
+        p.m_bx = magic(lay.BX);
+        p.m_by = magic(lay.BY);
+        p.m_tx = magic(p.TX);
+        p.m_ty = magic(p.TY);
+        for (int ps = 0; ps < passes; ++ps) {
+            const uint32_t lo = (uint32_t)ps + 1;
+            const uint32_t Wx = lay.BX - 2 * lo, Wy = lay.BY - 2 * lo;
+            const bool cb = L->desc.nbr == HMC_VN4 || L->desc.nbr == HMC_VN6;
+            p.m_pass[ps][0] = magic(Wx / 2);
+            p.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
+        }
+        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds);
         p.src = L->spins[L->cur];
         p.dst = L->spins[L->cur ^ 1];
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        void* args[] = {&p};
         if (L->profiling) {
+            // Events bound to the dispatch itself: they time the kernel, not
+            // the queue around it.
             if (L->events_used == L->events.size()) {
                 hipEvent_t a, b;
                 HMC_HIP(hipEventCreate(&a));
                 HMC_HIP(hipEventCreate(&b));
                 L->events.emplace_back(a, b);
             }
-            e0 = L->events[L->events_used].first;
-            e1 = L->events[L->events_used].second;
-            ++L->events_used;
-            HMC_HIP(hipEventRecord(e0, L->stream));
-        }
-        void* args[] = {&p};
-        HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream));
-        if (L->profiling) {
-            HMC_HIP(hipEventRecord(e1, L->stream));
+            const auto& ev = L->events[L->events_used++];
+            HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream, ev.first,
+                                       ev.second, 0));
             L->prof_launches += 1;
             L->prof_su += (int64_t)k * L->N;
+        } else {
+            HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream));
         }
         L->cur ^= 1;
         t_next += (uint64_t)k;
