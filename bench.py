@@ -6,8 +6,8 @@ the grain statistics (grain count, mean area, Schmid-bin area fractions).
 Inputs are resident in HBM before timing starts.
 
 Printed: one JSON line with site-updates/s (the metric), the roofline entry
-of the sweep kernel (its average launch duration from HIP events recorded
-around every launch on the lattice's stream, against MI355X peak HBM
+of the sweep kernel (its average launch duration from HIP events bound to
+every sweep dispatch on the lattice's stream, against MI355X peak HBM
 bandwidth, with the algorithmic bytes per site update stated below) and the
 CPU oracle timed on the host cores on a bounded sample of the same job.
 
@@ -48,8 +48,29 @@ def parse():
     ap.add_argument("--tiling", default="", help="tx,ty,tz,k (default: library choice)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-kib", default="", help="FETCH_SIZE,WRITE_SIZE KiB per launch (rocprof, scaled)")
     return ap.parse_args()
+
+
+def measured_traffic(workload, tiling):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when the kernel source or the tiling changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"sweep_tile_kernel_{workload}.md")
+    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "sweep.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "tiling"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    if fields.get("tiling") != ",".join(str(v) for v in tiling):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
@@ -125,11 +146,8 @@ def main():
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     su_per_launch = su / max(launches, 1)
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
-    traffic = None
-    if args.traffic_kib:
-        f, wr = (float(v) for v in args.traffic_kib.split(","))
-        traffic = (f + wr) * 1024.0
     tiling = lat.tiling()
+    traffic = measured_traffic(w.name, tiling)
 
     out = {
         "metric": "Potts site-updates/s (HBM GB/s vs peak in roofline), 1 MI355X, bit-exact vs oracle",
@@ -161,6 +179,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBPS,
             "traffic": traffic,
+            "traffic_note": "scaled FETCH_SIZE+WRITE_SIZE bytes per launch from profiles/ (null if the kernel changed)",
             "kernel": "sweep_tile_kernel",
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": launches,

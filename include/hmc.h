@@ -173,6 +173,61 @@ hmc_status hmc_profile_read(hmc_lattice *L, double *kernel_ms, int64_t *launches
 /* Wait for all work queued on the lattice's stream. */
 hmc_status hmc_synchronize(hmc_lattice *L);
 
+/* ------------------------------------------------------------ ensembles
+ * Many independent lattices (uneven sizes, temperatures and seeds) advanced
+ * together: one persistent kernel walks a ragged table of every member's
+ * tiles, each launch moves every member k MC steps, and the launch sequence
+ * of a call is captured once into a HIP graph and replayed.  Each member's
+ * result is exactly what hmc_sweep on that member alone would give (same
+ * Philox streams, same table), whatever the ensemble's tiling. */
+typedef struct hmc_ensemble_s hmc_ensemble;
+
+/* Borrow n >= 1 lattices that share neighbourhood, spin type and trial mode
+ * (sizes, Q, J_fx, energies may differ).  The lattices stay owned by the
+ * caller and must outlive the ensemble; free the ensemble first.  Errors:
+ * INVAL (NULL, n, mixed kinds, duplicate member), NOMEM, DEVICE. */
+hmc_status hmc_ensemble_create(hmc_lattice *const *lats, int32_t n, hmc_ensemble **out);
+
+/* Tile shape and MC steps per launch shared by all members (0 = automatic:
+ * autotuned entry if one is loaded, else a default).  Each tile side must
+ * divide the matching side of every member. */
+hmc_status hmc_ensemble_set_tiling(hmc_ensemble *E, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch);
+hmc_status hmc_ensemble_get_tiling(hmc_ensemble *E, int32_t *out4);
+
+/* n_mcs MC steps on every member; kT[i], seed[i] as in hmc_sweep for member
+ * i (host arrays of n entries).  Ordered after all work pending on the
+ * members' streams; members' later work waits for it.  Advances every
+ * member's MC counter by n_mcs.  Asynchronous. */
+hmc_status hmc_ensemble_sweep(hmc_ensemble *E, const float *kT, const uint64_t *seed, int32_t n_mcs);
+
+/* Wait for the ensemble's stream. */
+hmc_status hmc_ensemble_synchronize(hmc_ensemble *E);
+
+/* Time candidate tilings on the ensemble's own members (their spins and MC
+ * counters are restored afterwards), keep the fastest and return it in
+ * best_out4 (tx, ty, tz, k).  n_mcs per candidate; kT/seed as in
+ * hmc_ensemble_sweep.  Synchronous. */
+hmc_status hmc_ensemble_autotune(hmc_ensemble *E, const float *kT, const uint64_t *seed, int32_t n_mcs,
+                                 int32_t *best_out4);
+
+/* Release the ensemble (not its members).  NULL is a no-op. */
+hmc_status hmc_ensemble_free(hmc_ensemble *E);
+
+/* ------------------------------------------------------------ autotuner
+ * Time candidate tilings (tile sides x MC steps per launch) of hmc_sweep on
+ * a scratch lattice with this descriptor, n_grains Voronoi grains and zero
+ * bulk energy at temperature kT, n_mcs steps per candidate.  The fastest is
+ * returned (best_out4 = tx, ty, tz, k; us_per_mcs_out its time per MC step),
+ * registered for lattices of this shape created afterwards in this process,
+ * and appended as one JSON line to cache_path when it is not NULL.
+ * Synchronous.  Errors: INVAL, NOMEM, DEVICE, and file errors as INVAL. */
+hmc_status hmc_autotune(const hmc_lattice_desc *desc, int32_t n_grains, float kT, int32_t n_mcs,
+                        const char *cache_path, int32_t *best_out4, double *us_per_mcs_out);
+
+/* Load tilings from a cache written by hmc_autotune (later lines win).
+ * Returns the number of entries read in *n_loaded. */
+hmc_status hmc_tuning_load(const char *cache_path, int32_t *n_loaded);
+
 #ifdef __cplusplus
 }
 #endif

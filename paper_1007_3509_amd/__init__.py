@@ -68,6 +68,16 @@ _SIGS = [
     ("hmc_profile_read", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]),
     ("hmc_synchronize", C.c_int32, [C.c_void_p]),
+    ("hmc_ensemble_create", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("hmc_ensemble_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    ("hmc_ensemble_get_tiling", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("hmc_ensemble_sweep", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("hmc_ensemble_synchronize", C.c_int32, [C.c_void_p]),
+    ("hmc_ensemble_autotune", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hmc_ensemble_free", C.c_int32, [C.c_void_p]),
+    ("hmc_autotune", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_float, C.c_int32, C.c_char_p,
+                                 C.c_void_p, C.POINTER(C.c_double)]),
+    ("hmc_tuning_load", C.c_int32, [C.c_char_p, C.POINTER(C.c_int32)]),
 ]
 
 
@@ -212,6 +222,65 @@ def hmc_profile_read(h):
 
 def hmc_synchronize(h):
     _check(lib().hmc_synchronize(h))
+
+
+def _handles(lats):
+    hs = [l.h if isinstance(l, Lattice) else l for l in lats]
+    arr = (C.c_void_p * len(hs))(*[h.value if isinstance(h, C.c_void_p) else h for h in hs])
+    return arr, len(hs)
+
+
+def hmc_ensemble_create(lats):
+    arr, n = _handles(lats)
+    h = C.c_void_p()
+    _check(lib().hmc_ensemble_create(arr, n, C.byref(h)))
+    return h
+
+
+def hmc_ensemble_set_tiling(E, tx=0, ty=0, tz=0, mcs_per_launch=0):
+    _check(lib().hmc_ensemble_set_tiling(E, int(tx), int(ty), int(tz), int(mcs_per_launch)))
+
+
+def hmc_ensemble_get_tiling(E):
+    out = np.zeros(4, dtype=np.int32)
+    _check(lib().hmc_ensemble_get_tiling(E, _ptr(out)))
+    return tuple(int(v) for v in out)
+
+
+def hmc_ensemble_sweep(E, kT, seed, n_mcs):
+    k = np.ascontiguousarray(np.asarray(kT, dtype=np.float32))
+    s = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64))
+    _check(lib().hmc_ensemble_sweep(E, _ptr(k), _ptr(s), int(n_mcs)))
+
+
+def hmc_ensemble_synchronize(E):
+    _check(lib().hmc_ensemble_synchronize(E))
+
+
+def hmc_ensemble_autotune(E, kT, seed, n_mcs):
+    k = np.ascontiguousarray(np.asarray(kT, dtype=np.float32))
+    s = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.int32)
+    _check(lib().hmc_ensemble_autotune(E, _ptr(k), _ptr(s), int(n_mcs), _ptr(out)))
+    return tuple(int(v) for v in out)
+
+
+def hmc_ensemble_free(E):
+    _check(lib().hmc_ensemble_free(E))
+
+
+def hmc_autotune(desc, n_grains, kT, n_mcs, cache_path=None):
+    out = np.zeros(4, dtype=np.int32)
+    us = C.c_double()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().hmc_autotune(C.byref(desc), int(n_grains), float(kT), int(n_mcs), path, _ptr(out), C.byref(us)))
+    return tuple(int(v) for v in out), float(us.value)
+
+
+def hmc_tuning_load(cache_path):
+    n = C.c_int32()
+    _check(lib().hmc_tuning_load(str(cache_path).encode(), C.byref(n)))
+    return int(n.value)
 
 
 # --------------------------------------------------------- convenience class

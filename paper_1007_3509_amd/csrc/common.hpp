@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -177,8 +178,35 @@ struct hmc_lattice_s {
 
 namespace hmc {
 
+}  // namespace hmc
+
+struct hmc_ensemble_s {
+    std::vector<hmc_lattice*> lats;     // borrowed
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    hmc::Tiling tiling;                 // shared by all members
+    bool tiling_explicit = false;
+    bool prepared = false;
+    int32_t maxQ = 0;
+    void* d_tiles = nullptr;            // uint2 (lattice, tile) per tile
+    size_t tiles_bytes = 0;
+    uint32_t ntiles = 0;
+    void* d_lats = nullptr;             // one descriptor per member
+    size_t lats_bytes = 0;
+    uint32_t grid = 0;
+    std::map<int32_t, hipGraphExec_t> graphs;   // captured launch sequences by n_mcs
+    uint32_t graph_launches = 0;
+};
+
+namespace hmc {
+
 // Kernels (defined in their .hip files).
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed);
+hmc_status ensemble_prepare(hmc_ensemble* E);
+hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* seed, int32_t n_mcs);
+// Autotuned tiling for this lattice shape, or nullptr (tune.hip).
+const Tiling* tuned_tiling(const hmc_lattice_desc& d, int32_t Q);
+void record_tuning(const hmc_lattice_desc& d, const Tiling& t, double us_per_mcs);
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request);
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas

@@ -490,3 +490,98 @@ hmc_status hmc_synchronize(hmc_lattice* L) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ ensembles
+
+extern "C" {
+
+hmc_status hmc_ensemble_create(hmc_lattice* const* lats, int32_t n, hmc_ensemble** out) {
+    g_error.clear();
+    if (!out) return fail(HMC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!lats || n < 1) return fail(HMC_E_INVAL, "need at least one lattice");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!lats[i]) return fail(HMC_E_INVAL, "lattice " + std::to_string(i) + " is NULL");
+        const hmc_lattice* a = lats[i];
+        const hmc_lattice* b = lats[0];
+        if (a->desc.nbr != b->desc.nbr || a->desc.spin != b->desc.spin || a->desc.proposal != b->desc.proposal)
+            return fail(HMC_E_INVAL, "ensemble members must share neighbourhood, spin type and trial mode");
+        for (int32_t j = 0; j < i; ++j)
+            if (lats[j] == lats[i]) return fail(HMC_E_INVAL, "lattice " + std::to_string(i) + " appears twice");
+    }
+    hmc_ensemble* E = new hmc_ensemble();
+    E->lats.assign(lats, lats + n);
+    hipError_t e = hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (E->stream) (void)hipStreamDestroy(E->stream);
+        delete E;
+        return hip_fail(e, "ensemble stream");
+    }
+    *out = E;
+    return HMC_OK;
+}
+
+hmc_status hmc_ensemble_set_tiling(hmc_ensemble* E, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch) {
+    g_error.clear();
+    if (!E) return fail(HMC_E_INVAL, "ensemble is NULL");
+    if (tx < 0 || ty < 0 || tz < 0 || mcs_per_launch < 0) return fail(HMC_E_INVAL, "tiling values must be >= 0");
+    Tiling t;
+    t.tx = tx;
+    t.ty = ty;
+    t.tz = E->lats[0]->ndim == 3 ? tz : 1;
+    t.k = mcs_per_launch;
+    const Tiling old = E->tiling;
+    E->tiling = t;
+    E->prepared = false;
+    const hmc_status st = ensemble_prepare(E);
+    if (st != HMC_OK) {
+        E->tiling = old;
+        E->prepared = false;
+        return st;
+    }
+    return HMC_OK;
+}
+
+hmc_status hmc_ensemble_get_tiling(hmc_ensemble* E, int32_t* out4) {
+    g_error.clear();
+    if (!E || !out4) return fail(HMC_E_INVAL, "NULL argument");
+    if (!E->prepared) HMC_TRY(ensemble_prepare(E));
+    out4[0] = E->tiling.tx;
+    out4[1] = E->tiling.ty;
+    out4[2] = E->tiling.tz;
+    out4[3] = E->tiling.k;
+    return HMC_OK;
+}
+
+hmc_status hmc_ensemble_sweep(hmc_ensemble* E, const float* kT, const uint64_t* seed, int32_t n_mcs) {
+    g_error.clear();
+    if (!E || !kT || !seed) return fail(HMC_E_INVAL, "NULL argument");
+    if (n_mcs < 0) return fail(HMC_E_INVAL, "n_mcs must be >= 0");
+    for (size_t i = 0; i < E->lats.size(); ++i)
+        if (!(kT[i] > 0.0f) || !std::isfinite(kT[i]))
+            return fail(HMC_E_INVAL, "kT[" + std::to_string(i) + "] must be positive and finite");
+    return launch_ensemble(E, kT, seed, n_mcs);
+}
+
+hmc_status hmc_ensemble_synchronize(hmc_ensemble* E) {
+    g_error.clear();
+    if (!E) return fail(HMC_E_INVAL, "ensemble is NULL");
+    HMC_HIP(hipStreamSynchronize(E->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_ensemble_free(hmc_ensemble* E) {
+    g_error.clear();
+    if (!E) return HMC_OK;
+    (void)hipStreamSynchronize(E->stream);
+    for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
+    dev_free(E->d_tiles, E->tiles_bytes);
+    dev_free(E->d_lats, E->lats_bytes);
+    (void)hipEventDestroy(E->ev);
+    (void)hipStreamDestroy(E->stream);
+    delete E;
+    return HMC_OK;
+}
+
+}  // extern "C"

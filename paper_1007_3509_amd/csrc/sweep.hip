@@ -29,12 +29,19 @@
 //     sites, so SIMD lanes are not wasted on interior sites.
 //   * Acceptance is integer: d = J_fx*(c(q)-c(q')) + B[q'] - B[q], accept iff
 //     d <= 0 or r1 < T(d) from the host-built uint32 table.
+//
+// Ensemble mode (many independent lattices of uneven size, temperature and
+// seed): the same per-tile routine runs from a persistent kernel that walks
+// a ragged tile table covering every lattice; each launch advances every
+// lattice by k MC steps, and the launch sequence of a call is captured once
+// into a HIP graph and replayed.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 
 #include "common.hpp"
 
@@ -44,12 +51,13 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWave = 64;
-constexpr int kMaxRows = 64;        // threshold rows: at most 2M+1 = 53
-constexpr int kMaxPasses = 64;      // colour passes fused in one launch
+constexpr int kMaxRows = 64;         // threshold rows: at most 2M+1 = 53
+constexpr int kMaxPasses = 64;       // colour passes fused in one launch
 constexpr int kLdsGrainLimit = 4096; // grain energies staged in LDS up to this Q
-constexpr int kStaticLds = 8 + 8 * kMaxRows + 64;   // qcount + tbound + slack
+constexpr int kHeaderBytes = 16 + 8 * kMaxRows;   // queue counters + row bounds
 
-struct SweepParams {
+// Per-lattice arguments (uniform over a workgroup).
+struct LatArgs {
     const void* src;
     void* dst;
     const int32_t* B;
@@ -57,20 +65,31 @@ struct SweepParams {
     const uint32_t* Tb;       // per-row (lower, upper) bounds of T
     uint32_t Lx, Ly, Lz;
     uint32_t TX, TY, TZ;
-    uint32_t ntx, nty, ntz;
-    uint32_t BX, BY, BZ;      // LDS box (BZ = 1 in 2D)
-    uint32_t H;               // halo per side (= passes of this launch)
-    uint32_t P;               // passes in this launch
+    uint32_t ntx, nty;
     uint32_t t0;              // MC step index of the first pass
     uint32_t k0, k1;          // Philox key
     int32_t J_fx;
     int32_t Q;
     int32_t dn_lo, TW, R, rows;   // threshold-table layout
     uint32_t uniform;         // 1: symmetric trial spins
-    uint32_t xcd_group;       // tiles per XCD (0: identity mapping)
-    uint32_t queue_off, coord_off, grain_off;   // byte offsets in dynamic LDS
-    uint32_t m_bx, m_by, m_tx, m_ty;            // reciprocals (see magic())
-    uint32_t m_pass[kMaxPasses][2];             // per pass: per-row and rows reciprocals
+};
+
+// Per-launch arguments: the LDS box and its precomputed reciprocals.
+struct RunArgs {
+    uint32_t BX, BY, BZ;      // LDS box (BZ = 1 in 2D)
+    uint32_t H;               // halo per side (= passes of this launch)
+    uint32_t P;               // passes in this launch
+    uint32_t box_off, queue_off, coord_off, grain_off;   // byte offsets in dynamic LDS
+    uint32_t m_bx, m_by, m_tx, m_ty;
+    uint32_t m_pass[kMaxPasses][2];   // per pass: per-row and rows reciprocals
+};
+
+// Ensemble member as the device sees it.
+struct EnsLat {
+    LatArgs a;                // src/dst/t0 filled in by the kernel
+    void* buf[2];
+    uint32_t cur;             // buffer holding the state at the call's start
+    uint32_t t_base;          // MC step of the call's first step
 };
 
 template <int NBR>
@@ -103,70 +122,65 @@ __device__ __forceinline__ uint32_t wrap_coord(int64_t a, uint32_t L) {
 __host__ __device__ inline uint32_t magic(uint32_t d) { return d > 1 ? (uint32_t)(0x100000000ull / d) + 1u : 0u; }
 __device__ __forceinline__ uint32_t fdiv(uint32_t f, uint32_t m) { return m ? __umulhi(f, m) : f; }
 
+// One tile: stage tile + halo, run g.P colour passes in LDS, write the interior.
+// Ends with every thread past its last LDS access of the tile (callers that
+// process another tile put a barrier before reusing LDS).
 template <int NBR, typename Spin, bool kGrainsInLds>
-__global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
+__device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g, uint32_t tx, uint32_t ty,
+                                             uint32_t tz, unsigned char* smem) {
     using Tr = Traits<NBR>;
     constexpr int M = Tr::M, C = Tr::C, D = Tr::D;
     constexpr bool kCheckerboard = (NBR == HMC_VN4 || NBR == HMC_VN6);
     constexpr int kUnroll = 4;
 
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t qcount[2];
-    __shared__ uint32_t tbound[2 * kMaxRows];
-    Spin* box = reinterpret_cast<Spin*>(smem);
-    uint32_t* queue = reinterpret_cast<uint32_t*>(smem + p.queue_off);
-    uint32_t* gxs = reinterpret_cast<uint32_t*>(smem + p.coord_off);
-    uint32_t* gys = gxs + p.BX;
-    uint32_t* gzs = gys + p.BY;
-    int32_t* sB = reinterpret_cast<int32_t*>(smem + p.grain_off);
-    const int32_t* __restrict__ Bq = kGrainsInLds ? sB : p.B;
+    uint32_t* qcount = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* tbound = reinterpret_cast<uint32_t*>(smem + 16);
+    Spin* box = reinterpret_cast<Spin*>(smem + g.box_off);
+    uint32_t* queue = reinterpret_cast<uint32_t*>(smem + g.queue_off);
+    uint32_t* gxs = reinterpret_cast<uint32_t*>(smem + g.coord_off);
+    uint32_t* gys = gxs + g.BX;
+    uint32_t* gzs = gys + g.BY;
+    int32_t* sB = reinterpret_cast<int32_t*>(smem + g.grain_off);
+    const int32_t* __restrict__ Bq = kGrainsInLds ? sB : a.B;
 
-    const Spin* __restrict__ src = static_cast<const Spin*>(p.src);
-    Spin* __restrict__ dst = static_cast<Spin*>(p.dst);
+    const Spin* __restrict__ src = static_cast<const Spin*>(a.src);
+    Spin* __restrict__ dst = static_cast<Spin*>(a.dst);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
     const uint32_t nthr = blockDim.x;
 
-    // Tile of this workgroup.  Consecutive workgroups are spread over the 8
-    // XCDs round-robin; regroup so that each XCD gets a contiguous run of
-    // tiles and the halos it reads stay in its own L2.
-    uint32_t b = blockIdx.x;
-    if (p.xcd_group) b = (b & 7u) * p.xcd_group + (b >> 3);
-    const uint32_t tx = b % p.ntx;
-    const uint32_t ty = (b / p.ntx) % p.nty;
-    const uint32_t tz = b / (p.ntx * p.nty);
-    const uint32_t H = p.H;
+    const uint32_t H = g.H;
     const uint32_t Hz = (D == 3) ? H : 0u;
-    const int64_t x0 = (int64_t)tx * p.TX - (int64_t)H;
-    const int64_t y0 = (int64_t)ty * p.TY - (int64_t)H;
-    const int64_t z0 = (int64_t)tz * p.TZ - (int64_t)Hz;
+    const int64_t x0 = (int64_t)tx * a.TX - (int64_t)H;
+    const int64_t y0 = (int64_t)ty * a.TY - (int64_t)H;
+    const int64_t z0 = (int64_t)tz * a.TZ - (int64_t)Hz;
 
-    for (uint32_t u = tid; u < p.BX; u += nthr) gxs[u] = wrap_coord(x0 + u, p.Lx);
-    for (uint32_t v = tid; v < p.BY; v += nthr) gys[v] = wrap_coord(y0 + v, p.Ly);
-    for (uint32_t w = tid; w < p.BZ; w += nthr) gzs[w] = (D == 3) ? wrap_coord(z0 + w, p.Lz) : 0u;
-    for (uint32_t r = tid; r < 2u * (uint32_t)p.rows; r += nthr) tbound[r] = p.Tb[r];
+    for (uint32_t u = tid; u < g.BX; u += nthr) gxs[u] = wrap_coord(x0 + u, a.Lx);
+    for (uint32_t v = tid; v < g.BY; v += nthr) gys[v] = wrap_coord(y0 + v, a.Ly);
+    for (uint32_t w = tid; w < g.BZ; w += nthr) gzs[w] = (D == 3) ? wrap_coord(z0 + w, a.Lz) : 0u;
+    for (uint32_t r = tid; r < 2u * (uint32_t)a.rows; r += nthr) tbound[r] = a.Tb[r];
     if (kGrainsInLds)
-        for (uint32_t q = tid; q < (uint32_t)p.Q; q += nthr) sB[q] = p.B[q];
+        for (uint32_t q = tid; q < (uint32_t)a.Q; q += nthr) sB[q] = a.B[q];
     if (tid < 2) qcount[tid] = 0;
     __syncthreads();
 
     // Stage tile + halo: flat box index, consecutive threads on consecutive x
     // (coalesced), kUnroll independent loads in flight per thread.
-    const uint32_t box_n = p.BX * p.BY * p.BZ;
+    const uint32_t box_n = g.BX * g.BY * g.BZ;
     for (uint32_t e0 = tid; e0 < box_n; e0 += kUnroll * nthr) {
         int32_t v[kUnroll];
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             const uint32_t e = e0 + j * nthr;
             const uint32_t ec = e < box_n ? e : 0u;
-            const uint32_t r = fdiv(ec, p.m_bx);
-            const uint32_t u = ec - __umul24(r, p.BX);
-            const uint32_t w = (D == 3) ? fdiv(r, p.m_by) : 0u;
-            const uint32_t vv = r - __umul24(w, p.BY);
-            const uint32_t g = gxs[u] + p.Lx * (gys[vv] + p.Ly * gzs[w]);
-            v[j] = (int32_t)src[g];
+            const uint32_t r = fdiv(ec, g.m_bx);
+            const uint32_t u = ec - __umul24(r, g.BX);
+            const uint32_t w = (D == 3) ? fdiv(r, g.m_by) : 0u;
+            const uint32_t vv = r - __umul24(w, g.BY);
+            const uint32_t gi = gxs[u] + a.Lx * (gys[vv] + a.Ly * gzs[w]);
+            v[j] = (int32_t)src[gi];
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
@@ -179,25 +193,25 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
     int off[M];
 #pragma unroll
     for (int k = 0; k < M; ++k)
-        off[k] = nbr_dx(NBR, k) + nbr_dy(NBR, k) * (int)p.BX + nbr_dz(NBR, k) * (int)(p.BX * p.BY);
+        off[k] = nbr_dx(NBR, k) + nbr_dy(NBR, k) * (int)g.BX + nbr_dz(NBR, k) * (int)(g.BX * g.BY);
 
     // parities of box coordinate 0 along each axis (global coordinate parity)
     const uint32_t px = (uint32_t)(x0 & 1), py = (uint32_t)(y0 & 1), pz = (uint32_t)(z0 & 1);
 
-    for (uint32_t pass = 0; pass < p.P; ++pass) {
+    for (uint32_t pass = 0; pass < g.P; ++pass) {
         const uint32_t c = pass % C;
-        const uint32_t t = p.t0 + pass / C;
+        const uint32_t t = a.t0 + pass / C;
         const uint32_t lo = pass + 1;
         const uint32_t loz = (D == 3) ? lo : 0;
-        const uint32_t Wx = p.BX - 2 * lo;
-        const uint32_t Wy = p.BY - 2 * lo;
-        const uint32_t Wz = (D == 3) ? p.BZ - 2 * lo : 1;
+        const uint32_t Wx = g.BX - 2 * lo;
+        const uint32_t Wy = g.BY - 2 * lo;
+        const uint32_t Wz = (D == 3) ? g.BZ - 2 * lo : 1;
         // colour-class enumeration: sites per row, rows per plane, planes
         const uint32_t per_row = Wx / 2;
         const uint32_t rows = kCheckerboard ? Wy : Wy / 2;
         const uint32_t planes = (kCheckerboard || D == 2) ? Wz : Wz / 2;
         const uint32_t total = per_row * rows * planes;
-        const uint32_t m_row = p.m_pass[pass][0], m_rows = p.m_pass[pass][1];
+        const uint32_t m_row = g.m_pass[pass][0], m_rows = g.m_pass[pass][1];
         uint32_t* qc = &qcount[pass & 1];
         const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = (c >> 2) & 1u;
 
@@ -219,16 +233,16 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
                     if (kCheckerboard) {
                         v = lo + ri;
                         w = loz + pl;
-                        const uint32_t a = (lo + v + w + px + py + pz) & 1u;
-                        u = lo + 2 * jj + ((c ^ a) & 1u);
+                        const uint32_t par = (lo + v + w + px + py + pz) & 1u;
+                        u = lo + 2 * jj + ((c ^ par) & 1u);
                     } else {
                         u = lo + 2 * jj + ((cx ^ (lo + px)) & 1u);
                         v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
                         w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
                     }
-                    const uint32_t idx = u + __umul24(p.BX, v + __umul24(p.BY, w));
+                    const uint32_t idx = u + __umul24(g.BX, v + __umul24(g.BY, w));
                     const Spin s = box[idx];
-                    bool diff = p.uniform != 0;
+                    bool diff = a.uniform != 0;
 #pragma unroll
                     for (int k = 0; k < M; ++k) diff |= (box[(int)idx + off[k]] != s);
                     push[j] = diff;
@@ -258,40 +272,40 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
                 if (e >= count) continue;
                 const uint32_t packed = queue[e];
                 const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
-                const int idx = (int)(u + __umul24(p.BX, v + __umul24(p.BY, w)));
+                const int idx = (int)(u + __umul24(g.BX, v + __umul24(g.BY, w)));
                 const int32_t q = (int32_t)box[idx];
-                if ((uint32_t)q >= (uint32_t)p.Q) continue;
+                if ((uint32_t)q >= (uint32_t)a.Q) continue;
                 const int32_t bq = Bq[q];
-                const uint32_t site = gxs[u] + p.Lx * (gys[v] + p.Ly * gzs[w]);
-                const Philox2 r = philox_r01(site, t, c, 0u, p.k0, p.k1);
+                const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
+                const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
                 int32_t qn;
-                if (!p.uniform) {
+                if (!a.uniform) {
                     const uint32_t k = __umulhi(r.r0, (uint32_t)M);
                     int o = off[0];
 #pragma unroll
                     for (int kk = 1; kk < M; ++kk) o = (k == (uint32_t)kk) ? off[kk] : o;
                     qn = (int32_t)box[idx + o];
                 } else {
-                    qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(p.Q - 1));
-                    if (qn >= p.Q) qn -= p.Q;
+                    qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
+                    if (qn >= a.Q) qn -= a.Q;
                 }
-                if (qn == q || (uint32_t)qn >= (uint32_t)p.Q) continue;
+                if (qn == q || (uint32_t)qn >= (uint32_t)a.Q) continue;
                 int cq = 0, cn = 0;
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
-                    const int32_t s = (int32_t)box[idx + off[k]];
-                    cq += (s == q);
-                    cn += (s == qn);
+                    const int32_t sv = (int32_t)box[idx + off[k]];
+                    cq += (sv == q);
+                    cn += (sv == qn);
                 }
                 const int32_t dn = cq - cn;
                 const int32_t dB = Bq[qn] - bq;
-                const int32_t d = p.J_fx * dn + dB;
+                const int32_t d = a.J_fx * dn + dB;
                 bool accept = d <= 0;
                 if (!accept) {
                     // T is non-increasing in d: the row's bounds decide most trials
-                    const int row = dn - p.dn_lo;
+                    const int row = dn - a.dn_lo;
                     if (r.r1 < tbound[2 * row]) accept = true;
-                    else if (r.r1 < tbound[2 * row + 1]) accept = r.r1 < p.T[row * p.TW + dB + p.R];
+                    else if (r.r1 < tbound[2 * row + 1]) accept = r.r1 < a.T[row * a.TW + dB + a.R];
                 }
                 if (accept) box[idx] = (Spin)qn;
             }
@@ -300,20 +314,66 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(SweepParams p) {
     }
 
     // Interior back to global memory: flat over the tile, coalesced rows.
-    const uint32_t tile_n = p.TX * p.TY * p.TZ;
+    const uint32_t tile_n = a.TX * a.TY * a.TZ;
     const uint32_t gx0 = gxs[H];
     for (uint32_t e = tid; e < tile_n; e += nthr) {
-        const uint32_t r = fdiv(e, p.m_tx);
-        const uint32_t u = e - __umul24(r, p.TX);
-        const uint32_t w = (D == 3) ? fdiv(r, p.m_ty) : 0u;
-        const uint32_t vv = r - __umul24(w, p.TY);
-        const Spin val = box[(H + u) + __umul24(p.BX, (H + vv) + __umul24(p.BY, Hz + w))];
-        dst[gx0 + u + p.Lx * (gys[H + vv] + p.Ly * gzs[Hz + w])] = val;
+        const uint32_t r = fdiv(e, g.m_tx);
+        const uint32_t u = e - __umul24(r, a.TX);
+        const uint32_t w = (D == 3) ? fdiv(r, g.m_ty) : 0u;
+        const uint32_t vv = r - __umul24(w, a.TY);
+        const Spin val = box[(H + u) + __umul24(g.BX, (H + vv) + __umul24(g.BY, Hz + w))];
+        dst[gx0 + u + a.Lx * (gys[H + vv] + a.Ly * gzs[Hz + w])] = val;
+    }
+}
+
+// One lattice: one workgroup per tile.
+template <int NBR, typename Spin, bool kGrainsInLds>
+__global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs g, uint32_t xcd_group) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // Consecutive workgroups are spread over the 8 XCDs round-robin; regroup
+    // so that each XCD gets a contiguous run of tiles and the halos it reads
+    // stay in its own L2.
+    uint32_t b = blockIdx.x;
+    if (xcd_group) b = (b & 7u) * xcd_group + (b >> 3);
+    const uint32_t tx = b % a.ntx;
+    const uint32_t ty = (b / a.ntx) % a.nty;
+    const uint32_t tz = b / (a.ntx * a.nty);
+    process_tile<NBR, Spin, kGrainsInLds>(a, g, tx, ty, tz, smem);
+}
+
+// Ensemble: persistent workgroups walk the ragged tile table of all lattices.
+// tiles[i] = (lattice, tile index inside that lattice).  Launch j of a call
+// advances every lattice from MC step t_base + j*k.
+template <int NBR, typename Spin, bool kGrainsInLds>
+__global__ void __launch_bounds__(kThreads)
+ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, uint32_t ntiles,
+                uint32_t j, uint32_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (uint32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const uint2 tl = tiles[i];
+        const EnsLat& e = lats[tl.x];
+        LatArgs a = e.a;
+        const uint32_t sel = (e.cur ^ j) & 1u;
+        a.src = e.buf[sel];
+        a.dst = e.buf[sel ^ 1u];
+        a.t0 = e.t_base + j * k;
+        const uint32_t tx = tl.y % a.ntx;
+        const uint32_t ty = (tl.y / a.ntx) % a.nty;
+        const uint32_t tz = tl.y / (a.ntx * a.nty);
+        process_tile<NBR, Spin, kGrainsInLds>(a, g, tx, ty, tz, smem);
+        __syncthreads();
     }
 }
 
 template <int NBR>
-const void* kernel_for(int spin, bool grains_in_lds) {
+const void* kernel_for(int spin, bool grains_in_lds, bool ensemble) {
+    if (ensemble) {
+        if (spin == HMC_I16)
+            return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, true>)
+                                 : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, false>);
+        return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true>)
+                             : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false>);
+    }
     if (spin == HMC_I16)
         return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true>)
                              : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false>);
@@ -321,51 +381,133 @@ const void* kernel_for(int spin, bool grains_in_lds) {
                          : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false>);
 }
 
-const void* kernel_ptr(int nbr, int spin, bool grains_in_lds) {
+const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble) {
     switch (nbr) {
-    case HMC_VN4: return kernel_for<HMC_VN4>(spin, grains_in_lds);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8>(spin, grains_in_lds);
-    case HMC_VN6: return kernel_for<HMC_VN6>(spin, grains_in_lds);
-    default: return kernel_for<HMC_MOORE26>(spin, grains_in_lds);
+    case HMC_VN4: return kernel_for<HMC_VN4>(spin, grains_in_lds, ensemble);
+    case HMC_MOORE8: return kernel_for<HMC_MOORE8>(spin, grains_in_lds, ensemble);
+    case HMC_VN6: return kernel_for<HMC_VN6>(spin, grains_in_lds, ensemble);
+    default: return kernel_for<HMC_MOORE26>(spin, grains_in_lds, ensemble);
     }
 }
 
 struct Layout {
     uint32_t BX, BY, BZ, H;
-    size_t queue_off, coord_off, grain_off, bytes;
+    size_t box_off, queue_off, coord_off, grain_off, bytes;
     bool grains_in_lds;
 };
 
-Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
+// LDS layout of one tile: [counters | row bounds | box | queue | coords | grains].
+Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes) {
     Layout o{};
     o.H = (uint32_t)passes;
     o.BX = (uint32_t)(t.tx + 2 * passes);
     o.BY = (uint32_t)(t.ty + 2 * passes);
-    o.BZ = L->ndim == 3 ? (uint32_t)(t.tz + 2 * passes) : 1u;
+    o.BZ = ndim == 3 ? (uint32_t)(t.tz + 2 * passes) : 1u;
     const size_t elems = (size_t)o.BX * o.BY * o.BZ;
     size_t qcap;
-    switch (L->desc.nbr) {
+    switch (nbr) {
     case HMC_VN4: case HMC_VN6: qcap = elems / 2 + 1; break;
     case HMC_MOORE8: qcap = elems / 4 + 1; break;
     default: qcap = elems / 8 + 1; break;
     }
-    o.queue_off = (elems * L->spin_bytes + 15) / 16 * 16;
+    o.box_off = kHeaderBytes;
+    o.queue_off = o.box_off + (elems * spin_bytes + 15) / 16 * 16;
     o.coord_off = o.queue_off + (qcap * 4 + 15) / 16 * 16;
     o.grain_off = (o.coord_off + (size_t)(o.BX + o.BY + o.BZ) * 4 + 15) / 16 * 16;
     o.bytes = o.grain_off;
     o.grains_in_lds = false;
-    const size_t with_grains = o.grain_off + (size_t)L->Q * 4;
-    if (L->Q <= kLdsGrainLimit && (int64_t)with_grains + kStaticLds <= lds_limit_bytes()) {
+    const size_t with_grains = o.grain_off + (size_t)maxQ * 4;
+    if (maxQ <= kLdsGrainLimit && (int64_t)with_grains <= lds_limit_bytes()) {
         o.grains_in_lds = true;
         o.bytes = with_grains;
     }
     return o;
 }
 
+Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
+    return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes);
+}
+
+RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes) {
+    RunArgs g{};
+    g.BX = lay.BX; g.BY = lay.BY; g.BZ = lay.BZ;
+    g.H = lay.H;
+    g.P = (uint32_t)passes;
+    g.box_off = (uint32_t)lay.box_off;
+    g.queue_off = (uint32_t)lay.queue_off;
+    g.coord_off = (uint32_t)lay.coord_off;
+    g.grain_off = (uint32_t)lay.grain_off;
+    g.m_bx = magic(lay.BX);
+    g.m_by = magic(lay.BY);
+    g.m_tx = magic((uint32_t)t.tx);
+    g.m_ty = magic((uint32_t)t.ty);
+    const bool cb = nbr == HMC_VN4 || nbr == HMC_VN6;
+    for (int ps = 0; ps < passes; ++ps) {
+        const uint32_t lo = (uint32_t)ps + 1;
+        const uint32_t Wx = lay.BX - 2 * lo, Wy = lay.BY - 2 * lo;
+        g.m_pass[ps][0] = magic(Wx / 2);
+        g.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
+    }
+    return g;
+}
+
+LatArgs lat_args(const hmc_lattice* L, const Tiling& t, uint64_t seed) {
+    const int* dims = L->desc.dims;
+    LatArgs a{};
+    a.B = L->dB;
+    a.T = L->table.dev;
+    a.Tb = L->table.bounds;
+    a.rows = L->table.rows;
+    a.Lx = (uint32_t)dims[0];
+    a.Ly = (uint32_t)dims[1];
+    a.Lz = L->ndim == 3 ? (uint32_t)dims[2] : 1u;
+    a.TX = (uint32_t)t.tx;
+    a.TY = (uint32_t)t.ty;
+    a.TZ = L->ndim == 3 ? (uint32_t)t.tz : 1u;
+    a.ntx = a.Lx / a.TX;
+    a.nty = a.Ly / a.TY;
+    a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(seed >> 32);
+    a.J_fx = L->desc.J_fx;
+    a.Q = L->Q;
+    a.dn_lo = L->table.dn_lo;
+    a.TW = L->table.TW;
+    a.R = L->table.R;
+    a.uniform = L->desc.proposal == HMC_PROP_UNIFORM ? 1u : 0u;
+    return a;
+}
+
 int largest_even_divisor_at_most(int L, int target) {
     for (int d = std::min(L, target) & ~1; d >= 2; d -= 2)
         if (L % d == 0) return d;
     return 2;
+}
+
+hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t maxQ, const int* dims, const Tiling& r) {
+    const int sides[3] = {r.tx, r.ty, r.tz};
+    for (int ax = 0; ax < ndim; ++ax) {
+        if (sides[ax] < 2 || sides[ax] % 2 != 0 || dims[ax] % sides[ax] != 0)
+            return fail(HMC_E_INVAL, "tile side " + std::to_string(sides[ax]) +
+                                         " must be an even divisor of the lattice side " + std::to_string(dims[ax]));
+    }
+    if (r.k < 1 || r.k * C > kMaxPasses)
+        return fail(HMC_E_INVAL, "mcs_per_launch * colours must be in [1, " + std::to_string(kMaxPasses) + "]");
+    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, r.k * C);
+    if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
+        return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
+    if ((int64_t)lay.bytes > lds_limit_bytes())
+        return fail(HMC_E_INVAL, "tile + halo needs " + std::to_string(lay.bytes) + " B of LDS, limit " +
+                                     std::to_string(lds_limit_bytes()));
+    return HMC_OK;
+}
+
+void default_tiling(int nbr, int& tile2, int& tile3, int& k) {
+    switch (nbr) {
+    case HMC_VN4: tile2 = 64; tile3 = 16; k = 4; break;
+    case HMC_MOORE8: tile2 = 64; tile3 = 16; k = 2; break;
+    case HMC_VN6: tile2 = 64; tile3 = 16; k = 1; break;
+    default: tile2 = 64; tile3 = 8; k = 1; break;
+    }
 }
 
 }  // namespace
@@ -387,34 +529,20 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
     const int* dims = L->desc.dims;
     Tiling r = t;
     if (!explicit_request || r.tx == 0 || r.ty == 0 || (L->ndim == 3 && r.tz == 0) || r.k == 0) {
-        int tile2 = 64, tile3 = 16, k = 1;
-        switch (L->desc.nbr) {
-        case HMC_VN4: tile2 = 64; k = 4; break;
-        case HMC_MOORE8: tile2 = 64; k = 2; break;
-        case HMC_VN6: tile3 = 16; k = 1; break;
-        default: tile3 = 8; k = 1; break;
+        int tile2, tile3, k;
+        default_tiling(L->desc.nbr, tile2, tile3, k);
+        const Tiling* tuned = tuned_tiling(L->desc, L->Q);
+        if (tuned && r.tx == 0 && r.ty == 0 && r.tz == 0 && r.k == 0) {
+            r = *tuned;
+        } else {
+            if (r.tx == 0) r.tx = largest_even_divisor_at_most(dims[0], L->ndim == 2 ? tile2 : tile3);
+            if (r.ty == 0) r.ty = largest_even_divisor_at_most(dims[1], L->ndim == 2 ? tile2 : tile3);
+            if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], tile3);
+            if (r.k == 0) r.k = k;
         }
-        if (r.tx == 0) r.tx = largest_even_divisor_at_most(dims[0], L->ndim == 2 ? tile2 : tile3);
-        if (r.ty == 0) r.ty = largest_even_divisor_at_most(dims[1], L->ndim == 2 ? tile2 : tile3);
-        if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], tile3);
-        if (r.k == 0) r.k = k;
     }
     if (L->ndim == 2) r.tz = 1;
-    const int sides[3] = {r.tx, r.ty, r.tz};
-    for (int a = 0; a < L->ndim; ++a) {
-        if (sides[a] < 2 || sides[a] % 2 != 0 || dims[a] % sides[a] != 0)
-            return fail(HMC_E_INVAL, "tile side " + std::to_string(sides[a]) +
-                                         " must be an even divisor of the lattice side " + std::to_string(dims[a]));
-    }
-    if (r.k < 1 || r.k * L->C > kMaxPasses)
-        return fail(HMC_E_INVAL, "mcs_per_launch * colours must be in [1, " + std::to_string(kMaxPasses) + "]");
-    const int passes = r.k * L->C;
-    const Layout lay = box_layout(L, r, passes);
-    if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
-        return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
-    if ((int64_t)lay.bytes + kStaticLds > lds_limit_bytes())
-        return fail(HMC_E_INVAL, "tile + halo needs " + std::to_string(lay.bytes) + " B of LDS, limit " +
-                                     std::to_string(lds_limit_bytes()));
+    HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, L->Q, dims, r));
     t = r;
     return HMC_OK;
 }
@@ -427,31 +555,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
     L->tiling = t;
 
-    const int* dims = L->desc.dims;
-    SweepParams p{};
-    p.B = L->dB;
-    p.T = L->table.dev;
-    p.Tb = L->table.bounds;
-    p.rows = L->table.rows;
-    p.Lx = (uint32_t)dims[0];
-    p.Ly = (uint32_t)dims[1];
-    p.Lz = L->ndim == 3 ? (uint32_t)dims[2] : 1u;
-    p.TX = (uint32_t)t.tx;
-    p.TY = (uint32_t)t.ty;
-    p.TZ = L->ndim == 3 ? (uint32_t)t.tz : 1u;
-    p.ntx = p.Lx / p.TX;
-    p.nty = p.Ly / p.TY;
-    p.ntz = p.Lz / p.TZ;
-    p.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
-    p.k1 = (uint32_t)(seed >> 32);
-    p.J_fx = L->desc.J_fx;
-    p.Q = L->Q;
-    p.dn_lo = L->table.dn_lo;
-    p.TW = L->table.TW;
-    p.R = L->table.R;
-    p.uniform = L->desc.proposal == HMC_PROP_UNIFORM ? 1u : 0u;
-    const uint32_t ntiles = p.ntx * p.nty * p.ntz;
-    p.xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
+    LatArgs a = lat_args(L, t, seed);
+    const uint32_t ntiles = a.ntx * a.nty * (a.Lz / a.TZ);
+    const uint32_t xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
 
     int32_t remaining = n_mcs;
     uint64_t t_next = L->mcs;
@@ -459,36 +565,21 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const int k = std::min<int32_t>(t.k, remaining);
         const int passes = k * L->C;
         const Layout lay = box_layout(L, t, passes);
-        p.BX = lay.BX; p.BY = lay.BY; p.BZ = lay.BZ;
-        p.H = lay.H;
-        p.P = (uint32_t)passes;
-        p.t0 = (uint32_t)t_next;
-        p.queue_off = (uint32_t)lay.queue_off;
-        p.coord_off = (uint32_t)lay.coord_off;
-        p.grain_off = (uint32_t)lay.grain_off;
-        p.m_bx = magic(lay.BX);
-        p.m_by = magic(lay.BY);
-        p.m_tx = magic(p.TX);
-        p.m_ty = magic(p.TY);
-        for (int ps = 0; ps < passes; ++ps) {
-            const uint32_t lo = (uint32_t)ps + 1;
-            const uint32_t Wx = lay.BX - 2 * lo, Wy = lay.BY - 2 * lo;
-            const bool cb = L->desc.nbr == HMC_VN4 || L->desc.nbr == HMC_VN6;
-            p.m_pass[ps][0] = magic(Wx / 2);
-            p.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
-        }
-        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds);
-        p.src = L->spins[L->cur];
-        p.dst = L->spins[L->cur ^ 1];
-        void* args[] = {&p};
+        RunArgs g = run_args(lay, L->desc.nbr, t, passes);
+        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false);
+        a.src = L->spins[L->cur];
+        a.dst = L->spins[L->cur ^ 1];
+        a.t0 = (uint32_t)t_next;
+        uint32_t xg = xcd_group;
+        void* args[] = {&a, &g, &xg};
         if (L->profiling) {
             // Events bound to the dispatch itself: they time the kernel, not
             // the queue around it.
             if (L->events_used == L->events.size()) {
-                hipEvent_t a, b;
-                HMC_HIP(hipEventCreate(&a));
-                HMC_HIP(hipEventCreate(&b));
-                L->events.emplace_back(a, b);
+                hipEvent_t e0, e1;
+                HMC_HIP(hipEventCreate(&e0));
+                HMC_HIP(hipEventCreate(&e1));
+                L->events.emplace_back(e0, e1);
             }
             const auto& ev = L->events[L->events_used++];
             HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream, ev.first,
@@ -503,6 +594,129 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         remaining -= k;
     }
     L->mcs += (uint64_t)n_mcs;
+    return HMC_OK;
+}
+
+// ------------------------------------------------------------------ ensemble
+
+hmc_status ensemble_prepare(hmc_ensemble* E) {
+    hmc_lattice* L0 = E->lats[0];
+    int32_t maxQ = 0;
+    std::vector<int> g(3, 0);
+    for (hmc_lattice* L : E->lats) {
+        maxQ = std::max(maxQ, L->Q);
+        for (int ax = 0; ax < L0->ndim; ++ax) g[ax] = std::gcd(g[ax], L->desc.dims[ax]);
+    }
+    E->maxQ = maxQ;
+    if (E->tiling.tx == 0 || E->tiling.k == 0) {
+        int tile2, tile3, k;
+        default_tiling(L0->desc.nbr, tile2, tile3, k);
+        Tiling t;
+        t.tx = largest_even_divisor_at_most(g[0], L0->ndim == 2 ? tile2 : tile3);
+        t.ty = largest_even_divisor_at_most(g[1], L0->ndim == 2 ? tile2 : tile3);
+        t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], tile3) : 1;
+        t.k = k;
+        E->tiling = t;
+    }
+    for (hmc_lattice* L : E->lats)
+        HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, maxQ, L->desc.dims, E->tiling));
+    // ragged tile table: every tile of every lattice
+    std::vector<uint2> tiles;
+    for (size_t i = 0; i < E->lats.size(); ++i) {
+        const hmc_lattice* L = E->lats[i];
+        const uint32_t n = (uint32_t)(L->desc.dims[0] / E->tiling.tx) * (uint32_t)(L->desc.dims[1] / E->tiling.ty) *
+                           (uint32_t)(L->ndim == 3 ? L->desc.dims[2] / E->tiling.tz : 1);
+        for (uint32_t tIdx = 0; tIdx < n; ++tIdx) tiles.push_back(make_uint2((uint32_t)i, tIdx));
+    }
+    E->ntiles = (uint32_t)tiles.size();
+    dev_free(E->d_tiles, E->tiles_bytes);
+    E->d_tiles = nullptr;
+    E->tiles_bytes = tiles.size() * sizeof(uint2);
+    HMC_TRY(dev_alloc(&E->d_tiles, E->tiles_bytes, "ensemble tile table"));
+    HMC_HIP(hipMemcpy(E->d_tiles, tiles.data(), E->tiles_bytes, hipMemcpyHostToDevice));
+    if (!E->d_lats) {
+        E->lats_bytes = E->lats.size() * sizeof(EnsLat);
+        HMC_TRY(dev_alloc(&E->d_lats, E->lats_bytes, "ensemble descriptors"));
+    }
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C);
+    const int per_cu = std::max(1, std::min(2, (int)(lds_limit_bytes() * 2 / std::max<size_t>(lay.bytes, 1))));
+    E->grid = std::max(1u, std::min(E->ntiles, (uint32_t)(cus * per_cu)));
+    for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
+    E->graphs.clear();
+    E->prepared = true;
+    return HMC_OK;
+}
+
+hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* seed, int32_t n_mcs) {
+    if (n_mcs == 0) return HMC_OK;
+    if (!E->prepared) HMC_TRY(ensemble_prepare(E));
+    hmc_lattice* L0 = E->lats[0];
+    const int C = L0->C;
+    // order after every member's pending work
+    for (hmc_lattice* L : E->lats) {
+        HMC_HIP(hipEventRecord(E->ev, L->stream));
+        HMC_HIP(hipStreamWaitEvent(E->stream, E->ev, 0));
+    }
+    std::vector<EnsLat> h(E->lats.size());
+    for (size_t i = 0; i < E->lats.size(); ++i) {
+        hmc_lattice* L = E->lats[i];
+        HMC_TRY(build_table(L->table, kT[i], L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
+        if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
+        h[i].a = lat_args(L, E->tiling, seed[i]);
+        h[i].buf[0] = L->spins[0];
+        h[i].buf[1] = L->spins[1];
+        h[i].cur = (uint32_t)L->cur;
+        h[i].t_base = (uint32_t)L->mcs;
+    }
+    HMC_HIP(hipMemcpyAsync(E->d_lats, h.data(), E->lats_bytes, hipMemcpyHostToDevice, E->stream));
+    HMC_HIP(hipStreamSynchronize(E->stream));
+
+    auto it = E->graphs.find(n_mcs);
+    if (it == E->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        HMC_HIP(hipStreamBeginCapture(E->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        int32_t remaining = n_mcs;
+        uint32_t j = 0;
+        const uint32_t kfull = (uint32_t)E->tiling.k;
+        while (remaining > 0 && err == hipSuccess) {
+            const int k = std::min<int32_t>(E->tiling.k, remaining);
+            const int passes = k * C;
+            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes);
+            RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes);
+            const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true);
+            const EnsLat* dl = static_cast<const EnsLat*>(E->d_lats);
+            const uint2* dt = static_cast<const uint2*>(E->d_tiles);
+            uint32_t nt = E->ntiles, jj = j, kk = kfull;
+            void* args[] = {&g, &dl, &dt, &nt, &jj, &kk};
+            err = hipLaunchKernel(kfn, dim3(E->grid), dim3(kThreads), args, lay.bytes, E->stream);
+            remaining -= k;
+            ++j;
+        }
+        const hipError_t e2 = hipStreamEndCapture(E->stream, &graph);
+        if (err != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(err, "ensemble capture");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+        it = E->graphs.emplace(n_mcs, exec).first;
+        E->graph_launches = j;
+    }
+    const uint32_t launches = (uint32_t)((n_mcs + E->tiling.k - 1) / E->tiling.k);
+    HMC_HIP(hipGraphLaunch(it->second, E->stream));
+    HMC_HIP(hipEventRecord(E->ev, E->stream));
+    for (hmc_lattice* L : E->lats) {
+        HMC_HIP(hipStreamWaitEvent(L->stream, E->ev, 0));
+        L->cur ^= (int)(launches & 1u);
+        L->mcs += (uint64_t)n_mcs;
+    }
     return HMC_OK;
 }
 
