@@ -48,6 +48,19 @@ def lib():
         L.orc_voronoi_brute.argtypes = [C.c_int, i32p, C.c_int32, C.c_uint64, i32p]
         L.orc_voronoi_grid.argtypes = [C.c_int, i32p, C.c_int32, C.c_uint64, i32p, C.c_int]
         L.orc_texture.argtypes = [i32p, C.c_int64, C.c_int32, i32p, C.c_int32, i64p, i32p, f64p, f64p]
+        L.orc_mcp_one.argtypes = [f64p, f64p, C.c_uint64, C.c_uint64, f64p, f64p, C.POINTER(C.c_int), f64p]
+        L.orc_mcp_one.restype = C.c_double
+        L.orc_mcp_solve.argtypes = [f64p, f64p, C.c_int64, C.c_uint64, C.c_uint64, f64p, f64p, f64p, C.c_int]
+        L.orc_mcp_select.argtypes = [f64p, C.c_int, C.c_double]
+        L.orc_mcp_tau_c.argtypes = [C.c_double]
+        L.orc_mcp_tau_c.restype = C.c_double
+        L.orc_mcp_shear_modulus.restype = C.c_double
+        L.orc_mcp_slip_systems.argtypes = [f64p, f64p]
+        L.orc_mlp_forward.argtypes = [f64p, f64p, C.c_int64, f64p]
+        L.orc_mlp_loss_grad.argtypes = [f64p, f64p, f64p, C.c_int64, f64p]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_adam_step.argtypes = [f64p, f64p, f64p, f64p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double]
         _lib = L
     return _lib
 
@@ -161,6 +174,79 @@ def texture(spins, Q, grain_bin=None, n_bins=0):
     if rc != 0:
         raise ValueError("texture: spin out of range")
     return areas, int(ng.value), float(mean.value), frac[:n_bins].copy()
+
+
+# ------------------------------------------------ crystal plasticity (Sec. 2)
+
+MCP_TAU0, MCP_TAUS, MCP_H0, MCP_BETA = 8.0, 122.0, 440.0, 1000.0
+MLP_PARAMS = 64 * 9 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a if n is None else a.reshape(n)
+
+
+def mcp_one(euler, eps6, seed, sample=0):
+    """One crystal: (E_rho [MPa], tau_c, accumulated slip, sub-steps, crystal-frame stress[6])."""
+    e, s = _f64(euler, 3), _f64(eps6, 6)
+    tc, gm, sig = C.c_double(), C.c_double(), np.zeros(6)
+    K = C.c_int()
+    E = lib().orc_mcp_one(_ptr(e, C.c_double), _ptr(s, C.c_double), int(seed), int(sample), C.byref(tc),
+                          C.byref(gm), C.byref(K), _ptr(sig, C.c_double))
+    return E, tc.value, gm.value, K.value, sig
+
+
+def mcp_solve(euler, eps6, seed, sample0=0, threads=1):
+    """Many crystals: (E_rho, tau_c, accumulated slip) arrays."""
+    e = _f64(euler).reshape(-1, 3)
+    s = _f64(eps6).reshape(-1, 6)
+    n = e.shape[0]
+    E, tc, gm = np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_mcp_solve(_ptr(e, C.c_double), _ptr(s, C.c_double), n, int(seed), int(sample0),
+                        _ptr(E, C.c_double), _ptr(tc, C.c_double), _ptr(gm, C.c_double), int(threads))
+    return E, tc, gm
+
+
+def mcp_select(p, R):
+    """Eq. (2): the slip system chosen by R from probabilities p."""
+    pa = _f64(p)
+    return lib().orc_mcp_select(_ptr(pa, C.c_double), len(pa), float(R))
+
+
+def mcp_tau_c(gamma):
+    return lib().orc_mcp_tau_c(float(gamma))
+
+
+def mcp_shear_modulus():
+    return lib().orc_mcp_shear_modulus()
+
+
+def mcp_slip_systems():
+    n, d = np.zeros((12, 3)), np.zeros((12, 3))
+    lib().orc_mcp_slip_systems(_ptr(n, C.c_double), _ptr(d, C.c_double))
+    return n, d
+
+
+def mlp_forward(theta, X):
+    th, x = _f64(theta), _f64(X).reshape(-1, 9)
+    y = np.empty(x.shape[0])
+    lib().orc_mlp_forward(_ptr(th, C.c_double), _ptr(x, C.c_double), x.shape[0], _ptr(y, C.c_double))
+    return y
+
+
+def mlp_loss_grad(theta, X, t):
+    th, x, tt = _f64(theta), _f64(X).reshape(-1, 9), _f64(t)
+    g = np.empty(MLP_PARAMS)
+    loss = lib().orc_mlp_loss_grad(_ptr(th, C.c_double), _ptr(x, C.c_double), _ptr(tt, C.c_double), x.shape[0],
+                                   _ptr(g, C.c_double))
+    return loss, g
+
+
+def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on theta, m, v (float64 arrays)."""
+    lib().orc_adam_step(_ptr(theta, C.c_double), _ptr(_f64(g), C.c_double), _ptr(m, C.c_double),
+                        _ptr(v, C.c_double), int(t), float(lr), float(b1), float(b2), float(eps))
 
 
 def available_threads():
