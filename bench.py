@@ -34,7 +34,9 @@ WORKLOADS = {
     "voronoi_2d_64": synth.voronoi_2d_64,
     "schmid_2d_1024": synth.schmid_2d_1024,
     "schmid_3d_256": synth.schmid_3d_256,
+    "stress_2d_16384": synth.stress_2d_16384,
 }
+SPECIAL = ("ensemble_moore8", "learned_3d_256")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}
 
 
@@ -43,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="schmid_2d_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="schmid_2d_1024", choices=sorted(WORKLOADS) + list(SPECIAL))
     ap.add_argument("--mcs", type=int, default=0, help="override MC steps per job")
     ap.add_argument("--tiling", default="", help="tx,ty,tz,k (default: library choice)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
@@ -109,6 +111,10 @@ def main():
     if hmc.hmc_device_count() < 1:
         print(json.dumps({"error": "no HIP device visible"}))
         sys.exit(1)
+    if args.workload == "ensemble_moore8":
+        return bench_ensemble(args, hmc)
+    if args.workload == "learned_3d_256":
+        return bench_learned(args, hmc)
     w = WORKLOADS[args.workload]()
     n_mcs = args.mcs or w.n_mcs
     lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
@@ -197,6 +203,141 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, start.astype(np.int32), n_mcs, args.cpu_seconds, gpu_check)
     lat.close()
     print(json.dumps(out), flush=True)
+
+
+def _line(metric, value, args, ms, config, **extra):
+    out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args, hmc):
+    """64 Moore-8 lattices of uneven size, temperature and seed: one ensemble
+    call (persistent kernel, HIP-graph replay) against the same lattices swept
+    one after another with hmc_sweep."""
+    members = synth.ensemble_moore8()
+    n_mcs = args.mcs or members[0].n_mcs
+    lats = []
+    for w in members:
+        lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
+        lat.set_grain_energy(w.B)
+        hmc.hmc_snapshot(lat.h)
+        lats.append(lat)
+    kT = np.array([w.kT for w in members], np.float32)
+    seeds = np.array([w.sweep_seed for w in members], np.uint64)
+    E = hmc.hmc_ensemble_create(lats)
+    tiling = hmc.hmc_ensemble_get_tiling(E)
+    total_sites = sum(w.n_sites for w in members)
+
+    def restore():
+        for lat in lats:
+            hmc.hmc_restore(lat.h)
+
+    def ens_step():
+        restore()
+        hmc.hmc_ensemble_sweep(E, kT, seeds, n_mcs)
+        hmc.hmc_ensemble_synchronize(E)
+
+    def single_step():
+        restore()
+        for lat, w in zip(lats, members):
+            lat.sweep(w.kT, n_mcs, w.sweep_seed)
+        for lat in lats:
+            lat.synchronize()
+
+    res = {}
+    for name, fn in (("ensemble", ens_step), ("one_by_one", single_step)):
+        for _ in range(args.warmup):
+            fn()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    # the ensemble's result equals the one-by-one result
+    ens_step()
+    a = [lat.spins() for lat in lats]
+    single_step()
+    same = all(np.array_equal(x, lat.spins()) for x, lat in zip(a, lats))
+    hmc.hmc_ensemble_free(E)
+    for lat in lats:
+        lat.close()
+    su = total_sites * n_mcs
+    _line("Potts site-updates/s, 64-lattice Moore-8 ensemble, 1 MI355X", su / res["ensemble"], args,
+          res["ensemble"] * 1e3,
+          {"workload": "ensemble_moore8", "lattices": len(members), "sites": total_sites,
+           "mcs_per_step": n_mcs, "tiling": list(tiling)},
+          one_by_one={"value": su / res["one_by_one"], "ms_per_step": res["one_by_one"] * 1e3},
+          speedup_vs_one_by_one=res["one_by_one"] / res["ensemble"], ensemble_equals_one_by_one=same)
+
+
+def bench_learned(args, hmc):
+    """256^3 VN6 lattice whose grain bulk energies come from the stored
+    dislocation energy under a monotonic uniaxial strain, re-queried every 10
+    MC steps (50 queries over 500 steps): the trained network (with audit)
+    against the crystal-plasticity solver in the loop."""
+    w = synth.schmid_3d_256()
+    n_mcs = args.mcs or w.n_mcs
+    every = 10
+    n_q = n_mcs // every
+    # training data from the solver (outside the timed region)
+    n_train, n_test = 1000000, 20000
+    eu, ep = synth.crystal_inputs(n_train + n_test, 5005)
+    t0 = time.perf_counter()
+    Ey = hmc.hmc_mcp_solve(eu, ep, seed=50)
+    t_gen = time.perf_counter() - t0
+    M = hmc.hmc_mlp_create(7)
+    t0 = time.perf_counter()
+    loss = hmc.hmc_mlp_train(M, eu[:n_train], ep[:n_train], Ey[:n_train], epochs=50, batch=2048, lr=5e-3, seed=1)
+    t_train = time.perf_counter() - t0
+    pred = hmc.hmc_mlp_predict(M, eu[n_train:], ep[n_train:])
+    rel = np.abs(pred - Ey[n_train:]) / Ey[n_train:]
+    E_ref = float(Ey[:n_train].max())
+    scale = 0.15 / E_ref              # E_MC = 0.15 E_rho / max training E_rho
+    lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
+    hmc.hmc_snapshot(lat.h)
+    euler = w.euler
+
+    def job(mode):
+        hmc.hmc_restore(lat.h)
+        fallbacks, errs, tq = 0, [], 0.0
+        for k in range(n_q):
+            q0 = time.perf_counter()
+            _, used, err = hmc.hmc_surrogate_update(lat, M, euler, synth.uniaxial_strain(k + 1, n_q), scale,
+                                                    mode=mode, n_audit=64, audit_tol=0.25, seed=k)
+            tq += time.perf_counter() - q0
+            fallbacks += int(used)
+            errs.append(err)
+            lat.sweep(w.kT, every, w.sweep_seed)
+        lat.synchronize()
+        return fallbacks, errs, tq
+
+    res = {}
+    for name, mode in (("surrogate", 0), ("solver", 1)):
+        for _ in range(args.warmup):
+            job(mode)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fb, errs, tq = job(mode)
+        res[name] = ((time.perf_counter() - t0) / args.steps, fb, float(np.max(errs)), tq)
+        res[name + "_frac"] = lat.texture_stats(w.grain_bin, w.n_bins)[2]
+    drift = float(np.max(np.abs(res["surrogate_frac"] - res["solver_frac"])))
+    lat.close()
+    hmc.hmc_mlp_free(M)
+    su = w.n_sites * n_mcs
+    _line("Potts site-updates/s with learned stored energy (re-queried every 10 MCS), 1 MI355X",
+          su / res["surrogate"][0], args, res["surrogate"][0] * 1e3,
+          {"workload": "learned_3d_256", "lattice": "256x256x256", "neighbourhood": "VN6", "grains": w.n_grains,
+           "mcs_per_step": n_mcs, "queries": n_q},
+          solver_in_loop={"value": su / res["solver"][0], "ms_per_step": res["solver"][0] * 1e3,
+                          "query_ms": res["solver"][3] / n_q * 1e3},
+          surrogate={"query_ms": res["surrogate"][3] / n_q * 1e3, "fallbacks": res["surrogate"][1],
+                     "max_audit_rel_err": res["surrogate"][2],
+                     "held_out_rel_err_median": float(np.median(rel)),
+                     "held_out_rel_err_p95": float(np.percentile(rel, 95)), "train_loss": loss,
+                     "train_s": t_train, "solver_data_s": t_gen},
+          texture_fraction_drift_max=drift)
 
 
 if __name__ == "__main__":

@@ -228,6 +228,87 @@ hmc_status hmc_autotune(const hmc_lattice_desc *desc, int32_t n_grains, float kT
  * Returns the number of entries read in *n_loaded. */
 hmc_status hmc_tuning_load(const char *cache_path, int32_t *n_loaded);
 
+/* ------------------------------------------- stored energy: solver and network
+ * The bulk energy of a grain is its stored dislocation energy (Sec. 3, Eq. (4):
+ * E_rho = rho G b^2 / 2 with rho = (2 sigma_f / (G b))^2 = 2 sigma_f^2 / G),
+ * produced by the Monte Carlo crystal-plasticity update of Sec. 2.  A small
+ * network trained on the solver's output can stand in for it. */
+
+/* Monte Carlo crystal plasticity (Sec. 2, Eqs. (1)-(2), Table 1 nickel
+ * constants) for n crystals, FP64 on the GPU, one thread per crystal.
+ * euler: n x 3 Bunge angles (phi1, Phi, phi2) of the passive sample->crystal
+ * rotation; eps: n x 6 total strain from the virgin crystal in the sample
+ * frame (e11, e22, e33, e23, e13, e12; tensor shear components), applied in
+ * K = ceil(max|e_ij| / 1e-5) <= 200 sub-steps.  One slip system per
+ * sub-step among those with |tau| > tau_c, chosen by Eq. (2) with
+ * p ~ exp(-1000/MPa * E_a) and R from Philox(key = seed,
+ * counter = (sample0 + i, step, 0, 0x4D435053)); Voce hardening
+ * (tau0 8, tau_s 122, h0 440 MPa).  Outputs E_out[i] = 2 tau_c^2 / G in MPa
+ * (G = (C11 - C12 + 3 C44) / 5) and optionally tau_c.  on_device: 1 if all
+ * four arrays are device pointers, 0 for host arrays.  Synchronous.
+ * Errors: INVAL (NULL, n < 0, n >= 2^31, non-finite strain), NOMEM, DEVICE. */
+hmc_status hmc_mcp_solve(const double *euler, const double *eps, int64_t n, uint64_t seed, uint64_t sample0,
+                         int32_t on_device, double *E_out, double *tauc_out);
+
+/* 9-64-64-1 tanh network predicting E_rho from (Bunge angles, strain).
+ * Features phi1/pi - 1, 2 Phi/pi - 1, phi2/pi - 1, e_ij / 2e-3; target
+ * standardised by the training mean and standard deviation (kept in the
+ * handle).  Parameters (4865 floats): W1[64][9], b1[64], W2[64][64], b2[64],
+ * w3[64], b3.  create: Xavier-uniform weights from Philox(seed), zero
+ * biases. */
+typedef struct hmc_mlp_s hmc_mlp;
+hmc_status hmc_mlp_create(uint64_t seed, hmc_mlp **out);
+hmc_status hmc_mlp_free(hmc_mlp *M);
+
+/* Host copies of the parameters (float[4865]) and of the target
+ * normalisation (double[2] = mean, std; may be NULL).  set_params resets
+ * Adam's moments and step. */
+hmc_status hmc_mlp_get_params(hmc_mlp *M, float *host_dst, double *norm_out);
+hmc_status hmc_mlp_set_params(hmc_mlp *M, const float *host_src, const double *norm);
+
+/* Train on n samples (euler n x 3, eps n x 6, E n in MPa; host or device
+ * per on_device) for `epochs` passes in mini-batches of `batch` (a multiple
+ * of 32), shuffled each epoch with Philox(seed); mean squared error on the
+ * standardised target; Adam with learning rate lr decaying on a cosine to
+ * lr/10.  final_loss (may be NULL): mean batch loss of the last epoch.
+ * Synchronous.  Errors: INVAL, NOMEM, DEVICE. */
+hmc_status hmc_mlp_train(hmc_mlp *M, const double *euler, const double *eps, const double *E, int64_t n,
+                         int32_t on_device, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                         float *final_loss);
+
+/* Predicted E_rho (MPa) for n crystals; arrays host or device per
+ * on_device.  Synchronous. */
+hmc_status hmc_mlp_predict(hmc_mlp *M, const double *euler, const double *eps, int64_t n, int32_t on_device,
+                           double *E_out);
+
+/* Standardised outputs for already-scaled features X (n x 9, host). */
+hmc_status hmc_mlp_forward(hmc_mlp *M, const float *X, int32_t n, float *y_out);
+
+/* Mean squared error over n samples (n a multiple of 32) of scaled features
+ * X (n x 9) and standardised targets t, and its gradient (float[4865]), by
+ * the training kernels; parameters unchanged.  Host arrays.  Synchronous. */
+hmc_status hmc_mlp_loss_grad(hmc_mlp *M, const float *X, const float *t, int32_t n, float *loss_out,
+                             float *grad_out);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with a host gradient. */
+hmc_status hmc_mlp_adam_step(hmc_mlp *M, const float *grad, float lr);
+
+/* Bulk energies of a lattice's grains from their stored energy under one
+ * macroscopic strain eps6 (6 components, sample frame): B[q] =
+ * round-half-even(E_rho[q] * E_scale * 65536), then as hmc_set_grain_energy.
+ * euler: host Q x 3 orientations of the grains.  mode 0: the network, with
+ * an audit of n_audit grains (drawn with Philox(seed)) against the solver;
+ * if the strain leaves the training box (|e_ij| > 2e-3), any prediction is
+ * not finite, or the largest relative audit error exceeds audit_tol, every
+ * grain is solved instead (*used_solver = 1).  mode 1: the solver for every
+ * grain (the method without the network; M may be NULL).  *audit_err gets
+ * the largest relative audit error (0 if no audit ran); B_out (may be NULL)
+ * receives the int32[Q] energies set.  Synchronous.
+ * Errors: INVAL, RANGE (energy range), NOMEM, DEVICE. */
+hmc_status hmc_surrogate_update(hmc_lattice *L, hmc_mlp *M, const double *euler, const double *eps6, double E_scale,
+                                int32_t mode, int32_t n_audit, double audit_tol, uint64_t seed,
+                                int32_t *used_solver, double *audit_err, int32_t *B_out);
+
 #ifdef __cplusplus
 }
 #endif

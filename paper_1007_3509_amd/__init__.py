@@ -78,6 +78,22 @@ _SIGS = [
     ("hmc_autotune", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_float, C.c_int32, C.c_char_p,
                                  C.c_void_p, C.POINTER(C.c_double)]),
     ("hmc_tuning_load", C.c_int32, [C.c_char_p, C.POINTER(C.c_int32)]),
+    ("hmc_mcp_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint64, C.c_int32,
+                                  C.c_void_p, C.c_void_p]),
+    ("hmc_mlp_create", C.c_int32, [C.c_uint64, C.POINTER(C.c_void_p)]),
+    ("hmc_mlp_free", C.c_int32, [C.c_void_p]),
+    ("hmc_mlp_get_params", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hmc_mlp_set_params", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hmc_mlp_train", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_float, C.c_uint64, C.POINTER(C.c_float)]),
+    ("hmc_mlp_predict", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    ("hmc_mlp_forward", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hmc_mlp_loss_grad", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_float),
+                                      C.c_void_p]),
+    ("hmc_mlp_adam_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_float]),
+    ("hmc_surrogate_update", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                         C.c_int32, C.c_double, C.c_uint64, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.c_void_p]),
 ]
 
 
@@ -281,6 +297,95 @@ def hmc_tuning_load(cache_path):
     n = C.c_int32()
     _check(lib().hmc_tuning_load(str(cache_path).encode(), C.byref(n)))
     return int(n.value)
+
+
+MLP_PARAMS = 4865
+
+
+def _f64(a, cols=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a if cols is None else a.reshape(-1, cols)
+
+
+def hmc_mcp_solve(euler, eps, seed, sample0=0, with_tauc=False):
+    e, p = _f64(euler, 3), _f64(eps, 6)
+    n = e.shape[0]
+    E = np.empty(n)
+    tc = np.empty(n) if with_tauc else None
+    _check(lib().hmc_mcp_solve(_ptr(e), _ptr(p), n, int(seed), int(sample0), 0, _ptr(E),
+                               None if tc is None else _ptr(tc)))
+    return (E, tc) if with_tauc else E
+
+
+def hmc_mlp_create(seed=0):
+    h = C.c_void_p()
+    _check(lib().hmc_mlp_create(int(seed), C.byref(h)))
+    return h
+
+
+def hmc_mlp_free(M):
+    _check(lib().hmc_mlp_free(M))
+
+
+def hmc_mlp_get_params(M):
+    th = np.empty(MLP_PARAMS, dtype=np.float32)
+    norm = np.empty(2)
+    _check(lib().hmc_mlp_get_params(M, _ptr(th), _ptr(norm)))
+    return th, norm
+
+
+def hmc_mlp_set_params(M, theta, norm=None):
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+    nm = None if norm is None else np.ascontiguousarray(np.asarray(norm, dtype=np.float64))
+    _check(lib().hmc_mlp_set_params(M, _ptr(th), None if nm is None else _ptr(nm)))
+
+
+def hmc_mlp_train(M, euler, eps, E, epochs, batch, lr, seed):
+    e, p, y = _f64(euler, 3), _f64(eps, 6), _f64(E)
+    loss = C.c_float()
+    _check(lib().hmc_mlp_train(M, _ptr(e), _ptr(p), _ptr(y), e.shape[0], 0, int(epochs), int(batch), float(lr),
+                               int(seed), C.byref(loss)))
+    return float(loss.value)
+
+
+def hmc_mlp_predict(M, euler, eps):
+    e, p = _f64(euler, 3), _f64(eps, 6)
+    out = np.empty(e.shape[0])
+    _check(lib().hmc_mlp_predict(M, _ptr(e), _ptr(p), e.shape[0], 0, _ptr(out)))
+    return out
+
+
+def hmc_mlp_forward(M, X):
+    x = np.ascontiguousarray(np.asarray(X, dtype=np.float32).reshape(-1, 9))
+    y = np.empty(x.shape[0], dtype=np.float32)
+    _check(lib().hmc_mlp_forward(M, _ptr(x), x.shape[0], _ptr(y)))
+    return y
+
+
+def hmc_mlp_loss_grad(M, X, t):
+    x = np.ascontiguousarray(np.asarray(X, dtype=np.float32).reshape(-1, 9))
+    tt = np.ascontiguousarray(np.asarray(t, dtype=np.float32))
+    g = np.empty(MLP_PARAMS, dtype=np.float32)
+    loss = C.c_float()
+    _check(lib().hmc_mlp_loss_grad(M, _ptr(x), _ptr(tt), x.shape[0], C.byref(loss), _ptr(g)))
+    return float(loss.value), g
+
+
+def hmc_mlp_adam_step(M, grad, lr):
+    g = np.ascontiguousarray(np.asarray(grad, dtype=np.float32))
+    _check(lib().hmc_mlp_adam_step(M, _ptr(g), float(lr)))
+
+
+def hmc_surrogate_update(L, M, euler, eps6, E_scale, mode=0, n_audit=64, audit_tol=0.05, seed=0):
+    h = L.h if isinstance(L, Lattice) else L
+    e = _f64(euler, 3)
+    p = _f64(eps6)
+    used = C.c_int32()
+    err = C.c_double()
+    B = np.empty(e.shape[0], dtype=np.int32)
+    _check(lib().hmc_surrogate_update(h, M, _ptr(e), _ptr(p), float(E_scale), int(mode), int(n_audit),
+                                      float(audit_tol), int(seed), C.byref(used), C.byref(err), _ptr(B)))
+    return B, bool(used.value), float(err.value)
 
 
 # --------------------------------------------------------- convenience class

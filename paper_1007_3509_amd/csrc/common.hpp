@@ -113,14 +113,18 @@ __host__ __device__ constexpr int nbr_dz(int nbr, int k) {
 // T(d) for every d > 0 the lattice can produce, laid out as
 // T[(dn - dn_lo) * TW + (dB + R)] with dn = c(q) - c(q'), dB = B[q'] - B[q],
 // R = max B - min B, TW = 2R + 1.
-// bounds[2*r] = T at the largest d of row r (lower bound of the row),
-// bounds[2*r+1] = T at the smallest positive d of row r (upper bound); T is
-// non-increasing in d, so most trials are decided by these two numbers.
+// Each row is split into nb buckets of bw consecutive columns; bounds[2*k]
+// is T at the largest d of bucket k (a lower bound of T over the bucket),
+// bounds[2*k+1] T at its smallest positive d (an upper bound).  T is
+// non-increasing in d, so a trial whose r1 falls outside [lower, upper) is
+// decided by the bucket's two numbers alone; kBoundPairs bounds the count.
+constexpr int kBoundPairs = 512;
 struct Table {
     uint32_t* dev = nullptr;      // rows * TW entries
-    uint32_t* bounds = nullptr;   // 2 * rows entries
+    uint32_t* bounds = nullptr;   // 2 * rows * nb entries
     size_t bytes = 0;             // allocation behind dev (bounds included)
     int32_t dn_lo = 0, rows = 0, R = 0, TW = 1;
+    int32_t nb = 1, bw = 1;       // buckets per row, columns per bucket
     uint32_t kT_bits = 0;
     int32_t Bmin = 0, Bmax = 0;
     bool valid = false;

@@ -7,6 +7,7 @@
 // C library exp and uploaded; kernels only compare integers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -103,20 +104,30 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     const int64_t rows = M - dn_lo + 1;
     const int64_t TW = 2 * R + 1;
     const size_t entries = (size_t)(rows * TW);
-    const size_t bytes = (entries + 2 * (size_t)rows) * sizeof(uint32_t);
+    // at least two columns per bucket unless the row has a single column
+    const int64_t nb = TW == 1 ? 1 : std::max<int64_t>(1, std::min<int64_t>(TW / 2, kBoundPairs / std::max<int64_t>(rows, 1)));
+    const int64_t bw = (TW + nb - 1) / nb;
+    const size_t nbound = 2 * (size_t)(rows * nb);
+    const size_t bytes = (entries + nbound) * sizeof(uint32_t);
     if (bytes > kTableCapBytes)
         return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
-    std::vector<uint32_t> host(entries + 2 * (size_t)rows, 0xFFFFFFFFu);
+    std::vector<uint32_t> host(entries + nbound, 0xFFFFFFFFu);
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t dn = dn_lo + r;
         for (int64_t j = 0; j < TW; ++j) {
             const int64_t d = (int64_t)J_fx * dn + (j - R);
             if (d > 0) host[(size_t)(r * TW + j)] = threshold_value(d, kT);
         }
-        const int64_t dmax = (int64_t)J_fx * dn + R;
-        const int64_t dmin = std::max<int64_t>(1, (int64_t)J_fx * dn - R);
-        host[entries + 2 * r] = dmax > 0 ? threshold_value(dmax, kT) : 0xFFFFFFFFu;
-        host[entries + 2 * r + 1] = dmax > 0 ? threshold_value(dmin, kT) : 0xFFFFFFFFu;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t c0 = b * bw, c1 = std::min<int64_t>(TW, (b + 1) * bw) - 1;
+            const int64_t dmax = (int64_t)J_fx * dn + (c1 - R);
+            const int64_t dmin = std::max<int64_t>(1, (int64_t)J_fx * dn + (c0 - R));
+            uint32_t* bd = &host[entries + 2 * (size_t)(r * nb + b)];
+            if (c0 <= c1 && dmax > 0) {
+                bd[0] = threshold_value(dmax, kT);
+                bd[1] = threshold_value(dmin, kT);
+            }
+        }
     }
     if (tab.bytes < bytes) {
         free_table(tab);
@@ -126,6 +137,8 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
         tab.bytes = bytes;
     }
     tab.bounds = tab.dev + entries;
+    tab.nb = (int32_t)nb;
+    tab.bw = (int32_t)bw;
     HMC_HIP(hipMemcpyAsync(tab.dev, host.data(), bytes, hipMemcpyHostToDevice, stream));
     HMC_HIP(hipStreamSynchronize(stream));
     tab.dn_lo = (int32_t)dn_lo;

@@ -54,7 +54,7 @@ constexpr int kWave = 64;
 constexpr int kMaxRows = 64;         // threshold rows: at most 2M+1 = 53
 constexpr int kMaxPasses = 64;       // colour passes fused in one launch
 constexpr int kLdsGrainLimit = 4096; // grain energies staged in LDS up to this Q
-constexpr int kHeaderBytes = 16 + 8 * kMaxRows;   // queue counters + row bounds
+constexpr int kHeaderBytes = 8 * kBoundPairs + 16;   // threshold bucket bounds + queue counters
 
 // Per-lattice arguments (uniform over a workgroup).
 struct LatArgs {
@@ -71,6 +71,8 @@ struct LatArgs {
     int32_t J_fx;
     int32_t Q;
     int32_t dn_lo, TW, R, rows;   // threshold-table layout
+    int32_t nb, nbound;       // buckets per row, bound pairs in total
+    uint32_t bw, m_bw;        // bucket width and its reciprocal (m_bw = 0: divide)
     uint32_t uniform;         // 1: symmetric trial spins
 };
 
@@ -122,6 +124,26 @@ __device__ __forceinline__ uint32_t wrap_coord(int64_t a, uint32_t L) {
 __host__ __device__ inline uint32_t magic(uint32_t d) { return d > 1 ? (uint32_t)(0x100000000ull / d) + 1u : 0u; }
 __device__ __forceinline__ uint32_t fdiv(uint32_t f, uint32_t m) { return m ? __umulhi(f, m) : f; }
 
+// Box offset of neighbour k (k from the trial draw, so not a constant),
+// computed from the neighbour order without an indexed table.
+template <int NBR>
+__device__ __forceinline__ int nbr_offset(uint32_t k, int BX, int BXY) {
+    if (NBR == HMC_MOORE26) {
+        const int m = (int)k + (k >= 13 ? 1 : 0);
+        const int dz = m / 9, rem = m - 9 * dz;
+        const int dy = rem / 3, dx = rem - 3 * dy;
+        return (dx - 1) + (dy - 1) * BX + (dz - 1) * BXY;
+    }
+    const int sgn = 1 - 2 * (int)(k & 1u);
+    if (NBR == HMC_MOORE8 && k >= 4) {
+        const int dy = (k < 6) ? sgn : -sgn;   // (+1,+1) (-1,-1) (+1,-1) (-1,+1)
+        return sgn + dy * BX;
+    }
+    const uint32_t axis = k >> 1;           // +x -x +y -y (+z -z)
+    const int stride = axis == 0 ? 1 : (axis == 1 ? BX : BXY);
+    return sgn * stride;
+}
+
 // One tile: stage tile + halo, run g.P colour passes in LDS, write the interior.
 // Ends with every thread past its last LDS access of the tile (callers that
 // process another tile put a barrier before reusing LDS).
@@ -133,8 +155,8 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     constexpr bool kCheckerboard = (NBR == HMC_VN4 || NBR == HMC_VN6);
     constexpr int kUnroll = 4;
 
-    uint32_t* qcount = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* tbound = reinterpret_cast<uint32_t*>(smem + 16);
+    uint32_t* tbound = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* qcount = reinterpret_cast<uint32_t*>(smem + kHeaderBytes - 16);
     Spin* box = reinterpret_cast<Spin*>(smem + g.box_off);
     uint32_t* queue = reinterpret_cast<uint32_t*>(smem + g.queue_off);
     uint32_t* gxs = reinterpret_cast<uint32_t*>(smem + g.coord_off);
@@ -156,18 +178,14 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     const int64_t x0 = (int64_t)tx * a.TX - (int64_t)H;
     const int64_t y0 = (int64_t)ty * a.TY - (int64_t)H;
     const int64_t z0 = (int64_t)tz * a.TZ - (int64_t)Hz;
-
     for (uint32_t u = tid; u < g.BX; u += nthr) gxs[u] = wrap_coord(x0 + u, a.Lx);
     for (uint32_t v = tid; v < g.BY; v += nthr) gys[v] = wrap_coord(y0 + v, a.Ly);
     for (uint32_t w = tid; w < g.BZ; w += nthr) gzs[w] = (D == 3) ? wrap_coord(z0 + w, a.Lz) : 0u;
-    for (uint32_t r = tid; r < 2u * (uint32_t)a.rows; r += nthr) tbound[r] = a.Tb[r];
+    for (uint32_t r = tid; r < 2u * (uint32_t)a.nbound; r += nthr) tbound[r] = a.Tb[r];
     if (kGrainsInLds)
         for (uint32_t q = tid; q < (uint32_t)a.Q; q += nthr) sB[q] = a.B[q];
     if (tid < 2) qcount[tid] = 0;
     __syncthreads();
-
-    // Stage tile + halo: flat box index, consecutive threads on consecutive x
-    // (coalesced), kUnroll independent loads in flight per thread.
     const uint32_t box_n = g.BX * g.BY * g.BZ;
     for (uint32_t e0 = tid; e0 < box_n; e0 += kUnroll * nthr) {
         int32_t v[kUnroll];
@@ -179,8 +197,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             const uint32_t u = ec - __umul24(r, g.BX);
             const uint32_t w = (D == 3) ? fdiv(r, g.m_by) : 0u;
             const uint32_t vv = r - __umul24(w, g.BY);
-            const uint32_t gi = gxs[u] + a.Lx * (gys[vv] + a.Ly * gzs[w]);
-            v[j] = (int32_t)src[gi];
+            v[j] = (int32_t)src[gxs[u] + a.Lx * (gys[vv] + a.Ly * gzs[w])];
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
@@ -197,6 +214,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 
     // parities of box coordinate 0 along each axis (global coordinate parity)
     const uint32_t px = (uint32_t)(x0 & 1), py = (uint32_t)(y0 & 1), pz = (uint32_t)(z0 & 1);
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
 
     for (uint32_t pass = 0; pass < g.P; ++pass) {
         const uint32_t c = pass % C;
@@ -212,10 +230,53 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         const uint32_t planes = (kCheckerboard || D == 2) ? Wz : Wz / 2;
         const uint32_t total = per_row * rows * planes;
         const uint32_t m_row = g.m_pass[pass][0], m_rows = g.m_pass[pass][1];
-        uint32_t* qc = &qcount[pass & 1];
         const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = (c >> 2) & 1u;
 
-        // ---- phase 1: queue the sites of colour c that can change
+        // Metropolis trial of one queued site (packed box coordinates).
+        auto trial = [&](uint32_t packed) __attribute__((always_inline)) {
+            const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
+            const int idx = (int)(u + __umul24(g.BX, v + __umul24(g.BY, w)));
+            const int32_t q = (int32_t)box[idx];
+            if ((uint32_t)q >= (uint32_t)a.Q) return;
+            const int32_t bq = Bq[q];
+            const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
+            const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
+            int32_t qn;
+            if (!a.uniform) {
+                const uint32_t k = __umulhi(r.r0, (uint32_t)M);
+                qn = (int32_t)box[idx + nbr_offset<NBR>(k, (int)g.BX, (int)(g.BX * g.BY))];
+            } else {
+                qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
+                if (qn >= a.Q) qn -= a.Q;
+            }
+            if (qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
+            int cq = 0, cn = 0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int32_t sv = (int32_t)box[idx + off[k]];
+                cq += (sv == q);
+                cn += (sv == qn);
+            }
+            const int32_t dn = cq - cn;
+            const int32_t dB = Bq[qn] - bq;
+            const int32_t d = a.J_fx * dn + dB;
+            bool accept = d <= 0;
+            if (!accept) {
+                // T is non-increasing in d: the bucket's bounds decide almost every trial
+                const int row = dn - a.dn_lo;
+                const uint32_t col = (uint32_t)(dB + a.R);
+                const uint32_t bucket = a.m_bw ? __umulhi(col, a.m_bw) : col / a.bw;
+                const uint32_t bk = (uint32_t)row * (uint32_t)a.nb + bucket;
+                if (r.r1 < tbound[2 * bk]) accept = true;
+                else if (r.r1 < tbound[2 * bk + 1]) accept = r.r1 < a.T[row * a.TW + (int)col];
+            }
+            if (accept) box[idx] = (Spin)qn;
+        };
+
+        // Phase 1: enumerate colour c (every lane busy) and queue, through
+        // one LDS atomic per wave, the sites that have a neighbour of another
+        // spin.  Phase 2: full-width trials over the queue.
+        uint32_t* qc = &qcount[pass & 1];
         for (uint32_t f0 = wave * kWave; f0 < total; f0 += 2 * nthr) {
             bool push[2];
             uint32_t packed[2];
@@ -256,58 +317,18 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     uint32_t base = 0;
                     if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
                     base = __shfl(base, 0);
-                    if (push[j]) queue[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = packed[j];
+                    if (push[j]) queue[base + (uint32_t)__popcll(mask & lanes_below)] = packed[j];
                 }
             }
         }
         __syncthreads();
-
-        // ---- phase 2: Metropolis trial for every queued site
         const uint32_t count = *qc;
         if (tid == 0) qcount[(pass + 1) & 1] = 0;
         for (uint32_t e0 = tid; e0 < count; e0 += 2 * nthr) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const uint32_t e = e0 + j * nthr;
-                if (e >= count) continue;
-                const uint32_t packed = queue[e];
-                const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
-                const int idx = (int)(u + __umul24(g.BX, v + __umul24(g.BY, w)));
-                const int32_t q = (int32_t)box[idx];
-                if ((uint32_t)q >= (uint32_t)a.Q) continue;
-                const int32_t bq = Bq[q];
-                const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
-                const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
-                int32_t qn;
-                if (!a.uniform) {
-                    const uint32_t k = __umulhi(r.r0, (uint32_t)M);
-                    int o = off[0];
-#pragma unroll
-                    for (int kk = 1; kk < M; ++kk) o = (k == (uint32_t)kk) ? off[kk] : o;
-                    qn = (int32_t)box[idx + o];
-                } else {
-                    qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
-                    if (qn >= a.Q) qn -= a.Q;
-                }
-                if (qn == q || (uint32_t)qn >= (uint32_t)a.Q) continue;
-                int cq = 0, cn = 0;
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const int32_t sv = (int32_t)box[idx + off[k]];
-                    cq += (sv == q);
-                    cn += (sv == qn);
-                }
-                const int32_t dn = cq - cn;
-                const int32_t dB = Bq[qn] - bq;
-                const int32_t d = a.J_fx * dn + dB;
-                bool accept = d <= 0;
-                if (!accept) {
-                    // T is non-increasing in d: the row's bounds decide most trials
-                    const int row = dn - a.dn_lo;
-                    if (r.r1 < tbound[2 * row]) accept = true;
-                    else if (r.r1 < tbound[2 * row + 1]) accept = r.r1 < a.T[row * a.TW + dB + a.R];
-                }
-                if (accept) box[idx] = (Spin)qn;
+                if (e < count) trial(queue[e]);
             }
         }
         __syncthreads();
@@ -396,7 +417,7 @@ struct Layout {
     bool grains_in_lds;
 };
 
-// LDS layout of one tile: [counters | row bounds | box | queue | coords | grains].
+// LDS layout of one tile: [bucket bounds, queue counters | box | queue | coords | grains].
 Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes) {
     Layout o{};
     o.H = (uint32_t)passes;
@@ -473,6 +494,14 @@ LatArgs lat_args(const hmc_lattice* L, const Tiling& t, uint64_t seed) {
     a.dn_lo = L->table.dn_lo;
     a.TW = L->table.TW;
     a.R = L->table.R;
+    a.nb = L->table.nb;
+    a.nbound = L->table.rows * L->table.nb;
+    a.bw = (uint32_t)L->table.bw;
+    // umulhi(col, m) = col / bw exactly while col * bw < 2^32 (bw >= 2); with a
+    // single column (bw = 1, col = 0) any m gives 0; otherwise m = 0 selects
+    // a plain division
+    if (a.bw == 1) a.m_bw = 1u;
+    else a.m_bw = (uint64_t)L->table.TW * (uint64_t)a.bw < (1ull << 32) ? magic(a.bw) : 0u;
     a.uniform = L->desc.proposal == HMC_PROP_UNIFORM ? 1u : 0u;
     return a;
 }

@@ -183,6 +183,12 @@ def schmid_3d_256():
     return schmid_3d(name="schmid_3d_256")
 
 
+def stress_2d_16384():
+    """16384^2 VN4 int16 (512 MiB per buffer, beyond the 256 MiB Infinity
+    Cache), 32000 grains with energies as schmid_2d_1024, kT 0.5, 100 MCS."""
+    return schmid_2d(side=16384, G=32000, seed=2003, n_mcs=100, vseed=7, sseed=7, name="stress_2d_16384")
+
+
 def ensemble_moore8(count=64, seed=4004, n_mcs=1000):
     rng = np.random.Generator(np.random.PCG64(seed))
     sides = rng.choice(np.array([128, 256, 512, 1024]), size=count)
@@ -223,3 +229,26 @@ def gaussian_orientation_energy(n_orient=91, width=46.0):
 def random_spins(dims, Q, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(0, Q, size=tuple(reversed(dims))).astype(np.int32)
+
+
+# ------------------------------------------------- learned driving force
+
+STRAIN_BOX = 2e-3
+
+
+def crystal_inputs(n, seed=5005, strain_box=STRAIN_BOX):
+    """Training inputs of the stored-energy surrogate: uniform SO(3)
+    orientations as Bunge angles (Shoemake quaternions, PCG64) and strain
+    components uniform in +-strain_box, (e11, e22, e33, e23, e13, e12)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    euler = matrix_to_bunge(quat_to_matrix(shoemake_quaternions(rng, n)))
+    eps = rng.uniform(-strain_box, strain_box, size=(n, 6))
+    return euler, eps
+
+
+def uniaxial_strain(k, n_queries=50, strain_box=STRAIN_BOX):
+    """Query k of a monotonic uniaxial path along x with lateral contraction,
+    diag(e, -e/2, -e/2) with e = (k / n_queries) * strain_box (the loading of
+    the paper's single-crystal test, Sec. 2, scaled to the training box)."""
+    e = (k / n_queries) * strain_box
+    return np.array([e, -e / 2, -e / 2, 0.0, 0.0, 0.0])
