@@ -147,7 +147,7 @@ __device__ __forceinline__ int nbr_offset(uint32_t k, int BX, int BXY) {
 // One tile: stage tile + halo, run g.P colour passes in LDS, write the interior.
 // Ends with every thread past its last LDS access of the tile (callers that
 // process another tile put a barrier before reusing LDS).
-template <int NBR, typename Spin, bool kGrainsInLds>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar>
 __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g, uint32_t tx, uint32_t ty,
                                              uint32_t tz, unsigned char* smem) {
     using Tr = Traits<NBR>;
@@ -232,19 +232,27 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         const uint32_t m_row = g.m_pass[pass][0], m_rows = g.m_pass[pass][1];
         const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = (c >> 2) & 1u;
 
-        // Metropolis trial of one queued site (packed box coordinates).
+        // Metropolis trial of one queued site (packed box coordinates).  All
+        // reads that do not depend on the random numbers (own spin and grain
+        // energy, every neighbour, the site index) are issued before Philox
+        // so that their latency overlaps it.
         auto trial = [&](uint32_t packed) __attribute__((always_inline)) {
             const uint32_t u = packed & 1023u, v = (packed >> 10) & 1023u, w = packed >> 20;
             const int idx = (int)(u + __umul24(g.BX, v + __umul24(g.BY, w)));
             const int32_t q = (int32_t)box[idx];
+            int32_t nb[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) nb[k] = (int32_t)box[idx + off[k]];
+            const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
             if ((uint32_t)q >= (uint32_t)a.Q) return;
             const int32_t bq = Bq[q];
-            const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
             const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
             int32_t qn;
             if (!a.uniform) {
                 const uint32_t k = __umulhi(r.r0, (uint32_t)M);
-                qn = (int32_t)box[idx + nbr_offset<NBR>(k, (int)g.BX, (int)(g.BX * g.BY))];
+                qn = nb[0];
+#pragma unroll
+                for (int kk = 1; kk < M; ++kk) qn = (k == (uint32_t)kk) ? nb[kk] : qn;
             } else {
                 qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
                 if (qn >= a.Q) qn -= a.Q;
@@ -253,9 +261,8 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             int cq = 0, cn = 0;
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                const int32_t sv = (int32_t)box[idx + off[k]];
-                cq += (sv == q);
-                cn += (sv == qn);
+                cq += (nb[k] == q);
+                cn += (nb[k] == qn);
             }
             const int32_t dn = cq - cn;
             const int32_t dB = Bq[qn] - bq;
@@ -277,47 +284,103 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         // one LDS atomic per wave, the sites that have a neighbour of another
         // spin.  Phase 2: full-width trials over the queue.
         uint32_t* qc = &qcount[pass & 1];
-        for (uint32_t f0 = wave * kWave; f0 < total; f0 += 2 * nthr) {
-            bool push[2];
-            uint32_t packed[2];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint32_t f = f0 + j * nthr + lane;
-                push[j] = false;
-                packed[j] = 0;
-                if (f < total) {
+        if constexpr (kSwar) {
+            // Checkerboard, 16-bit spins: a lane takes 4 consecutive sites of a
+            // row as one 64-bit word, XORs it with its four (six) neighbour
+            // words and tests the two colour-c fields.
+            const uint32_t s_lo = lo >> 2, s_hi = (g.BX - lo - 1) >> 2;
+            const uint32_t nseg = s_hi - s_lo + 1;
+            const uint32_t totalS = nseg * Wy * Wz;
+            const uint32_t plane = g.BX * g.BY;
+            const uint32_t pbase = (px + py + pz) & 1u;
+            for (uint32_t f0 = wave * kWave; f0 < totalS; f0 += nthr) {
+                const uint32_t f = f0 + lane;
+                bool pa = false, pb = false;
+                uint32_t qa = 0, qb = 0;
+                if (f < totalS) {
                     const uint32_t rr = fdiv(f, m_row);
-                    const uint32_t jj = f - __umul24(rr, per_row);
+                    const uint32_t sg = s_lo + (f - __umul24(rr, nseg));
                     const uint32_t pl = (D == 3) ? fdiv(rr, m_rows) : 0u;
-                    const uint32_t ri = rr - __umul24(pl, rows);
-                    uint32_t u, v, w;
-                    if (kCheckerboard) {
-                        v = lo + ri;
-                        w = loz + pl;
-                        const uint32_t par = (lo + v + w + px + py + pz) & 1u;
-                        u = lo + 2 * jj + ((c ^ par) & 1u);
+                    const uint32_t v = lo + (rr - __umul24(pl, Wy));
+                    const uint32_t w = loz + pl;
+                    const uint32_t row = __umul24(g.BX, v + __umul24(g.BY, w));
+                    const uint32_t u0 = 4 * sg;
+                    const uint64_t S = *reinterpret_cast<const uint64_t*>(box + row + u0);
+                    uint64_t x;
+                    if (a.uniform) {
+                        x = ~0ull;
                     } else {
-                        u = lo + 2 * jj + ((cx ^ (lo + px)) & 1u);
-                        v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
-                        w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
+                        const uint64_t Up = *reinterpret_cast<const uint64_t*>(box + row - g.BX + u0);
+                        const uint64_t Dn = *reinterpret_cast<const uint64_t*>(box + row + g.BX + u0);
+                        const uint64_t sL = (uint16_t)box[row + (u0 > 0 ? u0 - 1 : 0)];
+                        const uint64_t sR = (uint16_t)box[row + (u0 + 4 < g.BX ? u0 + 4 : g.BX - 1)];
+                        x = (S ^ ((S << 16) | sL)) | (S ^ ((S >> 16) | (sR << 48))) | (S ^ Up) | (S ^ Dn);
+                        if (D == 3) {
+                            const uint64_t Fr = *reinterpret_cast<const uint64_t*>(box + row - plane + u0);
+                            const uint64_t Bk = *reinterpret_cast<const uint64_t*>(box + row + plane + u0);
+                            x |= (S ^ Fr) | (S ^ Bk);
+                        }
                     }
-                    const uint32_t idx = u + __umul24(g.BX, v + __umul24(g.BY, w));
-                    const Spin s = box[idx];
-                    bool diff = a.uniform != 0;
-#pragma unroll
-                    for (int k = 0; k < M; ++k) diff |= (box[(int)idx + off[k]] != s);
-                    push[j] = diff;
-                    packed[j] = u | (v << 10) | (w << 20);
+                    const uint32_t k = (c ^ (v + w + pbase)) & 1u;   // first colour-c field
+                    const uint32_t ua = u0 + k, ub = u0 + k + 2;
+                    pa = ua >= lo && ua < g.BX - lo && ((x >> (16 * k)) & 0xFFFFull) != 0;
+                    pb = ub >= lo && ub < g.BX - lo && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
+                    qa = ua | (v << 10) | (w << 20);
+                    qb = ub | (v << 10) | (w << 20);
+                }
+                const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+                const uint32_t na = (uint32_t)__popcll(ma), n = na + (uint32_t)__popcll(mb);
+                if (n) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(qc, n);
+                    base = __shfl(base, 0);
+                    if (pa) queue[base + (uint32_t)__popcll(ma & lanes_below)] = qa;
+                    if (pb) queue[base + na + (uint32_t)__popcll(mb & lanes_below)] = qb;
                 }
             }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint64_t mask = __ballot(push[j]);
-                if (mask) {
-                    uint32_t base = 0;
-                    if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
-                    base = __shfl(base, 0);
-                    if (push[j]) queue[base + (uint32_t)__popcll(mask & lanes_below)] = packed[j];
+        } else {
+            for (uint32_t f0 = wave * kWave; f0 < total; f0 += 2 * nthr) {
+                bool push[2];
+                uint32_t packed[2];
+    #pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint32_t f = f0 + j * nthr + lane;
+                    push[j] = false;
+                    packed[j] = 0;
+                    if (f < total) {
+                        const uint32_t rr = fdiv(f, m_row);
+                        const uint32_t jj = f - __umul24(rr, per_row);
+                        const uint32_t pl = (D == 3) ? fdiv(rr, m_rows) : 0u;
+                        const uint32_t ri = rr - __umul24(pl, rows);
+                        uint32_t u, v, w;
+                        if (kCheckerboard) {
+                            v = lo + ri;
+                            w = loz + pl;
+                            const uint32_t par = (lo + v + w + px + py + pz) & 1u;
+                            u = lo + 2 * jj + ((c ^ par) & 1u);
+                        } else {
+                            u = lo + 2 * jj + ((cx ^ (lo + px)) & 1u);
+                            v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
+                            w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
+                        }
+                        const uint32_t idx = u + __umul24(g.BX, v + __umul24(g.BY, w));
+                        const Spin s = box[idx];
+                        bool diff = a.uniform != 0;
+    #pragma unroll
+                        for (int k = 0; k < M; ++k) diff |= (box[(int)idx + off[k]] != s);
+                        push[j] = diff;
+                        packed[j] = u | (v << 10) | (w << 20);
+                    }
+                }
+    #pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint64_t mask = __ballot(push[j]);
+                    if (mask) {
+                        uint32_t base = 0;
+                        if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
+                        base = __shfl(base, 0);
+                        if (push[j]) queue[base + (uint32_t)__popcll(mask & lanes_below)] = packed[j];
+                    }
                 }
             }
         }
@@ -348,7 +411,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 }
 
 // One lattice: one workgroup per tile.
-template <int NBR, typename Spin, bool kGrainsInLds>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar>
 __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs g, uint32_t xcd_group) {
     extern __shared__ __align__(16) unsigned char smem[];
     // Consecutive workgroups are spread over the 8 XCDs round-robin; regroup
@@ -359,13 +422,13 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs
     const uint32_t tx = b % a.ntx;
     const uint32_t ty = (b / a.ntx) % a.nty;
     const uint32_t tz = b / (a.ntx * a.nty);
-    process_tile<NBR, Spin, kGrainsInLds>(a, g, tx, ty, tz, smem);
+    process_tile<NBR, Spin, kGrainsInLds, kSwar>(a, g, tx, ty, tz, smem);
 }
 
 // Ensemble: persistent workgroups walk the ragged tile table of all lattices.
 // tiles[i] = (lattice, tile index inside that lattice).  Launch j of a call
 // advances every lattice from MC step t_base + j*k.
-template <int NBR, typename Spin, bool kGrainsInLds>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar>
 __global__ void __launch_bounds__(kThreads)
 ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, uint32_t ntiles,
                 uint32_t j, uint32_t k) {
@@ -381,33 +444,43 @@ ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restr
         const uint32_t tx = tl.y % a.ntx;
         const uint32_t ty = (tl.y / a.ntx) % a.nty;
         const uint32_t tz = tl.y / (a.ntx * a.nty);
-        process_tile<NBR, Spin, kGrainsInLds>(a, g, tx, ty, tz, smem);
+        process_tile<NBR, Spin, kGrainsInLds, kSwar>(a, g, tx, ty, tz, smem);
         __syncthreads();
     }
 }
 
-template <int NBR>
+template <int NBR, bool kSwar>
 const void* kernel_for(int spin, bool grains_in_lds, bool ensemble) {
     if (ensemble) {
         if (spin == HMC_I16)
-            return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, true>)
-                                 : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, false>);
-        return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true>)
-                             : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false>);
+            return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, true, kSwar>)
+                                 : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, false, kSwar>);
+        return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true, false>)
+                             : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false, false>);
     }
     if (spin == HMC_I16)
-        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true>)
-                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false>);
-    return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true>)
-                         : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false>);
+        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true, kSwar>)
+                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar>);
+    return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true, false>)
+                         : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false>);
 }
 
-const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble) {
+// The 64-bit phase-1 path needs 16-bit spins, a checkerboard and rows of a
+// multiple of 4 sites (8-byte aligned words).
+bool use_swar(int nbr, int spin, uint32_t BX) {
+    return spin == HMC_I16 && (nbr == HMC_VN4 || nbr == HMC_VN6) && BX % 4 == 0;
+}
+
+const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar) {
     switch (nbr) {
-    case HMC_VN4: return kernel_for<HMC_VN4>(spin, grains_in_lds, ensemble);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8>(spin, grains_in_lds, ensemble);
-    case HMC_VN6: return kernel_for<HMC_VN6>(spin, grains_in_lds, ensemble);
-    default: return kernel_for<HMC_MOORE26>(spin, grains_in_lds, ensemble);
+    case HMC_VN4:
+        return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble)
+                    : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble);
+    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble);
+    case HMC_VN6:
+        return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble)
+                    : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble);
+    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble);
     }
 }
 
@@ -449,7 +522,7 @@ Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
     return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes);
 }
 
-RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes) {
+RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool swar) {
     RunArgs g{};
     g.BX = lay.BX; g.BY = lay.BY; g.BZ = lay.BZ;
     g.H = lay.H;
@@ -466,8 +539,14 @@ RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes) {
     for (int ps = 0; ps < passes; ++ps) {
         const uint32_t lo = (uint32_t)ps + 1;
         const uint32_t Wx = lay.BX - 2 * lo, Wy = lay.BY - 2 * lo;
-        g.m_pass[ps][0] = magic(Wx / 2);
-        g.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
+        if (swar) {   // rows of 4-site segments
+            const uint32_t nseg = ((lay.BX - lo - 1) >> 2) - (lo >> 2) + 1;
+            g.m_pass[ps][0] = magic(nseg);
+            g.m_pass[ps][1] = magic(Wy);
+        } else {
+            g.m_pass[ps][0] = magic(Wx / 2);
+            g.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
+        }
     }
     return g;
 }
@@ -594,8 +673,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const int k = std::min<int32_t>(t.k, remaining);
         const int passes = k * L->C;
         const Layout lay = box_layout(L, t, passes);
-        RunArgs g = run_args(lay, L->desc.nbr, t, passes);
-        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false);
+        const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
+        RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
+        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar);
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
         a.t0 = (uint32_t)t_next;
@@ -715,8 +795,9 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
             const int k = std::min<int32_t>(E->tiling.k, remaining);
             const int passes = k * C;
             const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes);
-            RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes);
-            const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true);
+            const bool swar = use_swar(L0->desc.nbr, L0->desc.spin, lay.BX);
+            RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes, swar);
+            const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true, swar);
             const EnsLat* dl = static_cast<const EnsLat*>(E->d_lats);
             const uint2* dt = static_cast<const uint2*>(E->d_tiles);
             uint32_t nt = E->ntiles, jj = j, kk = kfull;
