@@ -96,6 +96,15 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
     out = oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, sample, w.sweep_seed, threads=threads)
     dt = time.perf_counter() - t0
     exact = bool(np.array_equal(gpu_check(sample), out))
+    # single-thread reference semantics on a quarter of the budget
+    t0 = time.perf_counter()
+    oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, 1, w.sweep_seed, threads=1)
+    per1 = time.perf_counter() - t0
+    sample1 = int(max(1, min(n_mcs, budget_s / 4 / max(per1, 1e-9))))
+    t0 = time.perf_counter()
+    out1 = oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, sample1, w.sweep_seed, threads=1)
+    dt1 = time.perf_counter() - t0
+    same_1t = bool(np.array_equal(out1, out)) if sample1 == sample else None
     return {
         "value": w.n_sites * sample / dt,
         "unit": "site-updates/s",
@@ -104,6 +113,8 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
         "sample": f"{w.name}: first {sample} of {n_mcs} MC steps from the same initial grains "
                   f"({w.n_sites * sample:.3g} site updates, {dt:.1f} s)",
         "gpu_bit_exact_on_sample": exact,
+        "single_core": {"value": w.n_sites * sample1 / dt1, "sample_mcs": sample1,
+                        "same_as_threaded": same_1t},
     }
 
 
@@ -129,6 +140,7 @@ def main():
     if args.tiling:
         lat.set_tiling(*[int(v) for v in args.tiling.split(",")])
     start = lat.spins()
+    fb_start = lat.boundary_sites() / w.n_sites
     hmc.hmc_snapshot(lat.h)
     gbin = w.grain_bin if w.n_bins else None
 
@@ -151,11 +163,14 @@ def main():
     # events would add several microseconds to every launch.
     hmc.hmc_profile(lat.h, True)
     hmc.hmc_profile_read(lat.h)          # reset counters
+    hmc.hmc_profile_trials(lat.h)
     for _ in range(args.steps):
         step()
     lat.synchronize()
     kernel_ms, launches, su = hmc.hmc_profile_read(lat.h)
+    trials = hmc.hmc_profile_trials(lat.h)
     hmc.hmc_profile(lat.h, False)
+    fb_end = lat.boundary_sites() / w.n_sites
 
     total_su = w.n_sites * n_mcs * args.steps
     elapsed = t1 - t0
@@ -206,6 +221,10 @@ def main():
             "launches": launches,
             "bytes_per_site_update": bytes_per_su,
             "site_updates_per_launch": su_per_launch,
+            "philox_calls_per_site_update": trials / max(su, 1),
+            "boundary_site_fraction": {"start": fb_start, "end": fb_end},
+            "work_note": "Philox calls = queued trials including the redundant halo work of fused steps; "
+                         "boundary fraction = sites with an unlike neighbour / N",
         },
         "final_grains": stats[0],
         "final_mean_area": stats[1],

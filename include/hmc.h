@@ -110,6 +110,19 @@ hmc_status hmc_lattice_create(const hmc_lattice_desc *desc, int32_t n_grains, vo
 hmc_status hmc_lattice_init(const hmc_lattice_desc *desc, int32_t n_grains, uint64_t voronoi_seed,
                             void *stream, hmc_lattice **out);
 
+/* As hmc_lattice_create, but over the caller's device buffer dev_spins
+ * (N spins of the descriptor's type, e.g. a torch tensor's storage), which
+ * the lattice borrows: it is neither cleared nor freed, the caller keeps it
+ * alive until hmc_lattice_free, and after every call that changes the spins
+ * the current state is back in it once the lattice's stream reaches that
+ * point (the library keeps a second buffer of its own for the sweep).
+ * Values outside [0, Q) are never changed, never proposed and not counted
+ * by the statistics.  Errors: INVAL (NULL, not device memory, allocation
+ * smaller than the lattice, misaligned, and as hmc_lattice_create), NOMEM,
+ * DEVICE. */
+hmc_status hmc_lattice_wrap(const hmc_lattice_desc *desc, void *dev_spins, int32_t n_grains, void *stream,
+                            hmc_lattice **out);
+
 /* Release a lattice (synchronises its stream first).  NULL is a no-op. */
 hmc_status hmc_lattice_free(hmc_lattice *L);
 
@@ -169,6 +182,17 @@ hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
  * profiling was enabled (or last read), and resets the sums. */
 hmc_status hmc_profile(hmc_lattice *L, int32_t enable);
 hmc_status hmc_profile_read(hmc_lattice *L, double *kernel_ms, int64_t *launches, int64_t *site_updates);
+
+/* Trials drawn (Philox calls: queued sites, including the redundant halo
+ * work of fused steps) by sweep launches made while profiling was enabled,
+ * since enabling or the last call; resets the count.  0 if profiling was
+ * never enabled.  Synchronous. */
+hmc_status hmc_profile_trials(hmc_lattice *L, int64_t *trials);
+
+/* Number of grain-boundary sites of the current spins: sites whose spin is
+ * in [0, Q) and differs from at least one of their M neighbours (the sites
+ * whose trials can change the state, Sec. 3).  Synchronous. */
+hmc_status hmc_boundary_sites(hmc_lattice *L, int64_t *n_out);
 
 /* Wait for all work queued on the lattice's stream. */
 hmc_status hmc_synchronize(hmc_lattice *L);
@@ -280,6 +304,14 @@ hmc_status hmc_mlp_train(hmc_mlp *M, const double *euler, const double *eps, con
  * on_device.  Synchronous. */
 hmc_status hmc_mlp_predict(hmc_mlp *M, const double *euler, const double *eps, int64_t n, int32_t on_device,
                            double *E_out);
+
+/* Inference on device memory, asynchronous on `stream` (NULL: the
+ * handle's own stream; another stream is first ordered after the handle's
+ * pending work).  X_dev: n x 9 scaled features (float, row-major); y_dev:
+ * n standardised outputs (float; E_rho = y * std + mean with the handle's
+ * normalisation).  Synchronise `stream` before freeing the handle.
+ * Errors: INVAL, DEVICE. */
+hmc_status hmc_mlp_infer(hmc_mlp *M, const float *X_dev, float *y_dev, int64_t n, void *stream);
 
 /* Standardised outputs for already-scaled features X (n x 9, host). */
 hmc_status hmc_mlp_forward(hmc_mlp *M, const float *X, int32_t n, float *y_out);

@@ -158,6 +158,17 @@ def voronoi(dims, G, vseed, method="grid", threads=1):
     return out.reshape(tuple(reversed(dims)))
 
 
+def boundary_sites(spins, nbr, dims, Q):
+    """Sites with a spin in [0, Q) and at least one unlike neighbour: the
+    only sites whose trial can change the state (Sec. 3)."""
+    s = np.ascontiguousarray(np.asarray(spins).astype(np.int32).reshape(-1))
+    d = _dims3(dims)
+    f = lib().orc_boundary_sites
+    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), C.c_int32]
+    f.restype = C.c_int64
+    return int(f(_ptr(s, C.c_int32), int(nbr), _ptr(d, C.c_int32), int(Q)))
+
+
 def texture(spins, Q, grain_bin=None, n_bins=0):
     """(areas[Q], n_grains, mean_area, frac[n_bins]) of a spin field."""
     s = np.ascontiguousarray(np.asarray(spins).astype(np.int32).reshape(-1))

@@ -487,3 +487,26 @@ int orc_texture(const int32_t *spins, int64_t N, int32_t Q, const int32_t *grain
     }
     return 0;
 }
+
+/* Grain-boundary sites (Sec. 3: with neighbour-spin trials only a site with
+ * a neighbour of another spin can change): sites whose spin is in [0, Q)
+ * and differs from at least one of its M neighbours. */
+int64_t orc_boundary_sites(const int32_t *spins, int nbr, const int32_t dims_in[3], int32_t Q)
+{
+    int off[26][3];
+    int64_t dims[3] = {dims_in[0], dims_in[1], dims_in[2]};
+    int M = orc_offsets(nbr, off), k;
+    int64_t x, y, z, count = 0;
+    for (z = 0; z < dims[2]; ++z)
+        for (y = 0; y < dims[1]; ++y)
+            for (x = 0; x < dims[0]; ++x) {
+                int32_t q = spins[x + dims[0] * (y + dims[1] * z)];
+                if (q < 0 || q >= Q) continue;
+                for (k = 0; k < M; ++k)
+                    if (spins[orc_neighbour_index(dims, off, k, x, y, z)] != q) {
+                        ++count;
+                        break;
+                    }
+            }
+    return count;
+}

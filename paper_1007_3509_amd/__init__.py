@@ -50,6 +50,8 @@ _SIGS = [
     ("hmc_lattice_create", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     ("hmc_lattice_init", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_uint64, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
+    ("hmc_lattice_wrap", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
     ("hmc_lattice_free", C.c_int32, [C.c_void_p]),
     ("hmc_set_grain_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
     ("hmc_sweep", C.c_int32, [C.c_void_p, C.c_float, C.c_int32, C.c_uint64]),
@@ -67,6 +69,8 @@ _SIGS = [
     ("hmc_profile", C.c_int32, [C.c_void_p, C.c_int32]),
     ("hmc_profile_read", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]),
+    ("hmc_profile_trials", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("hmc_boundary_sites", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("hmc_synchronize", C.c_int32, [C.c_void_p]),
     ("hmc_ensemble_create", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     ("hmc_ensemble_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
@@ -87,6 +91,7 @@ _SIGS = [
     ("hmc_mlp_train", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_float, C.c_uint64, C.POINTER(C.c_float)]),
     ("hmc_mlp_predict", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    ("hmc_mlp_infer", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     ("hmc_mlp_forward", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     ("hmc_mlp_loss_grad", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_float),
                                       C.c_void_p]),
@@ -154,6 +159,14 @@ def hmc_lattice_init(desc, n_grains, voronoi_seed, stream=None):
     h = C.c_void_p()
     _check(lib().hmc_lattice_init(C.byref(desc), int(n_grains), int(voronoi_seed), stream, C.byref(h)))
     return h
+
+
+def hmc_lattice_wrap(desc, dev_ptr, n_grains, stream=None):
+    """Lattice over a caller-owned device buffer (an integer device address,
+    e.g. a torch tensor's data_ptr()); the buffer must outlive the handle."""
+    h = C.c_void_p()
+    _check(lib().hmc_lattice_wrap(C.byref(desc), C.c_void_p(int(dev_ptr)), int(n_grains), stream, C.byref(h)))
+    return h.value
 
 
 def hmc_lattice_free(h):
@@ -234,6 +247,18 @@ def hmc_profile_read(h):
     su = C.c_int64()
     _check(lib().hmc_profile_read(h, C.byref(ms), C.byref(n), C.byref(su)))
     return float(ms.value), int(n.value), int(su.value)
+
+
+def hmc_profile_trials(h):
+    n = C.c_int64()
+    _check(lib().hmc_profile_trials(h, C.byref(n)))
+    return n.value
+
+
+def hmc_boundary_sites(h):
+    n = C.c_int64()
+    _check(lib().hmc_boundary_sites(h, C.byref(n)))
+    return n.value
 
 
 def hmc_synchronize(h):
@@ -355,6 +380,12 @@ def hmc_mlp_predict(M, euler, eps):
     return out
 
 
+def hmc_mlp_infer(M, X_dev_ptr, y_dev_ptr, n, stream=None):
+    """Device addresses in and out (scaled features n x 9 float32 -> n
+    standardised float32 outputs); asynchronous on `stream`."""
+    _check(lib().hmc_mlp_infer(M, C.c_void_p(int(X_dev_ptr)), C.c_void_p(int(y_dev_ptr)), int(n), stream))
+
+
 def hmc_mlp_forward(M, X):
     x = np.ascontiguousarray(np.asarray(X, dtype=np.float32).reshape(-1, 9))
     y = np.empty(x.shape[0], dtype=np.float32)
@@ -394,12 +425,14 @@ class Lattice:
     """Owns one hmc_lattice handle (same calls, numpy in and out)."""
 
     def __init__(self, dims, nbr, n_grains, voronoi_seed=None, spin=HMC_I16, proposal=HMC_PROP_NEIGHBOUR,
-                 J_fx=65536, stream=None):
+                 J_fx=65536, stream=None, dev_ptr=None):
         self.dims = tuple(int(d) for d in dims)
         self.nbr, self.spin, self.n_grains = int(nbr), int(spin), int(n_grains)
         self.dtype = np.int16 if spin == HMC_I16 else np.int32
         desc = make_desc(self.dims, nbr, spin, proposal, J_fx)
-        if voronoi_seed is None:
+        if dev_ptr is not None:
+            self.h = hmc_lattice_wrap(desc, dev_ptr, n_grains, stream)
+        elif voronoi_seed is None:
             self.h = hmc_lattice_create(desc, n_grains, stream)
         else:
             self.h = hmc_lattice_init(desc, n_grains, voronoi_seed, stream)
@@ -439,6 +472,9 @@ class Lattice:
 
     def tiling(self):
         return hmc_get_tiling(self.h)
+
+    def boundary_sites(self):
+        return hmc_boundary_sites(self.h)
 
     def synchronize(self):
         hmc_synchronize(self.h)

@@ -144,6 +144,8 @@ struct Tiling {
 
 }  // namespace hmc
 
+constexpr int kTrialSlots = 1024;   // spread of the profiling trial counters (power of two)
+
 struct hmc_lattice_s {
     hmc_lattice_desc desc{};
     int32_t Q = 0;
@@ -156,6 +158,7 @@ struct hmc_lattice_s {
 
     void* spins[2] = {nullptr, nullptr};
     int cur = 0;
+    bool borrowed = false;                  // spins[0] belongs to the caller
     void* snap = nullptr;
     uint64_t snap_mcs = 0;
     bool has_snap = false;
@@ -178,6 +181,8 @@ struct hmc_lattice_s {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
     int64_t prof_launches = 0, prof_su = 0;
+    unsigned long long* d_trials = nullptr;   // kTrialSlots counters of Philox draws while profiling
+    unsigned long long* d_count = nullptr;    // boundary-site count
 };
 
 namespace hmc {
@@ -213,6 +218,7 @@ const Tiling* tuned_tiling(const hmc_lattice_desc& d, int32_t Q);
 void record_tuning(const hmc_lattice_desc& d, const Tiling& t, double us_per_mcs);
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request);
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
+hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas
 hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins);
 int lds_limit_bytes();

@@ -67,7 +67,7 @@ constexpr int kHistThreads = 256;
 
 template <typename Spin>
 __global__ void __launch_bounds__(kHistThreads)
-histogram_kernel(const Spin* __restrict__ s, uint64_t N, uint32_t* __restrict__ areas) {
+histogram_kernel(const Spin* __restrict__ s, uint64_t N, uint32_t Q, uint32_t* __restrict__ areas) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // uniform trip count per wave so that the wave-level votes see all lanes
@@ -80,13 +80,45 @@ histogram_kernel(const Spin* __restrict__ s, uint64_t N, uint32_t* __restrict__ 
         const bool head = ok && (lane == 0 || prev != q);
         const uint64_t heads = __ballot(head);
         const uint64_t valid = __ballot(ok);
-        if (head) {
+        if (head && (uint32_t)q < Q) {   // values outside [0, Q) are not counted
             // run ends at the next head or at the last valid lane
             const uint64_t later = heads & ~((2ull << lane) - 1ull);
             const uint32_t end = later ? (uint32_t)__ffsll((long long)later) - 1u
                                        : 64u - (uint32_t)__clzll((long long)valid);
             atomicAdd(&areas[q], end - lane);
         }
+    }
+}
+
+// Sites (with a spin in [0, Q)) that have at least one neighbour holding
+// another value: the grain-boundary sites, the only ones whose trial can
+// change anything (Sec. 3).
+template <int NBR, typename Spin>
+__global__ void __launch_bounds__(kHistThreads)
+boundary_kernel(const Spin* __restrict__ s, uint32_t Lx, uint32_t Ly, uint32_t Lz, uint32_t Q,
+                unsigned long long* __restrict__ count) {
+    constexpr int M = NBR == HMC_VN4 ? 4 : NBR == HMC_MOORE8 ? 8 : NBR == HMC_VN6 ? 6 : 26;
+    const uint64_t N = (uint64_t)Lx * Ly * Lz;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t wave_base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (uint64_t b = wave_base; b < N; b += stride) {
+        const uint64_t i = b + (threadIdx.x & 63u);
+        bool hit = false;
+        if (i < N) {
+            const uint32_t x = (uint32_t)(i % Lx), y = (uint32_t)((i / Lx) % Ly), z = (uint32_t)(i / ((uint64_t)Lx * Ly));
+            const int32_t q = (int32_t)s[i];
+            if ((uint32_t)q < Q) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const uint32_t xn = (x + Lx + (uint32_t)nbr_dx(NBR, k)) % Lx;
+                    const uint32_t yn = (y + Ly + (uint32_t)nbr_dy(NBR, k)) % Ly;
+                    const uint32_t zn = (z + Lz + (uint32_t)nbr_dz(NBR, k)) % Lz;
+                    hit |= (int32_t)s[xn + (uint64_t)Lx * (yn + (uint64_t)Ly * zn)] != q;
+                }
+            }
+        }
+        const uint64_t mask = __ballot(hit);
+        if ((threadIdx.x & 63u) == 0 && mask) atomicAdd(count, (unsigned long long)__popcll(mask));
     }
 }
 
@@ -180,10 +212,36 @@ hmc_status launch_histogram(hmc_lattice* L) {
     const int grid = grid_for(N, kHistThreads, 4096);
     if (L->desc.spin == HMC_I16)
         histogram_kernel<int16_t><<<grid, kHistThreads, 0, L->stream>>>((const int16_t*)L->spins[L->cur], N,
-                                                                          L->d_areas);
+                                                                          (uint32_t)L->Q, L->d_areas);
     else
         histogram_kernel<int32_t><<<grid, kHistThreads, 0, L->stream>>>((const int32_t*)L->spins[L->cur], N,
-                                                                          L->d_areas);
+                                                                          (uint32_t)L->Q, L->d_areas);
+    HMC_HIP(hipGetLastError());
+    return HMC_OK;
+}
+
+hmc_status launch_boundary_count(hmc_lattice* L) {
+    HMC_HIP(hipMemsetAsync(L->d_count, 0, sizeof(unsigned long long), L->stream));
+    const uint32_t Lx = (uint32_t)L->desc.dims[0], Ly = (uint32_t)L->desc.dims[1];
+    const uint32_t Lz = L->ndim == 3 ? (uint32_t)L->desc.dims[2] : 1u;
+    const int grid = grid_for((uint64_t)L->N, kHistThreads, 4096);
+    const void* sp = L->spins[L->cur];
+    const uint32_t Q = (uint32_t)L->Q;
+    const bool i16 = L->desc.spin == HMC_I16;
+#define HMC_BOUNDARY(NB)                                                                                         \
+    if (i16)                                                                                                     \
+        boundary_kernel<NB, int16_t><<<grid, kHistThreads, 0, L->stream>>>((const int16_t*)sp, Lx, Ly, Lz, Q,     \
+                                                                            L->d_count);                          \
+    else                                                                                                         \
+        boundary_kernel<NB, int32_t><<<grid, kHistThreads, 0, L->stream>>>((const int32_t*)sp, Lx, Ly, Lz, Q,     \
+                                                                            L->d_count);
+    switch (L->desc.nbr) {
+        case HMC_VN4: HMC_BOUNDARY(HMC_VN4) break;
+        case HMC_MOORE8: HMC_BOUNDARY(HMC_MOORE8) break;
+        case HMC_VN6: HMC_BOUNDARY(HMC_VN6) break;
+        default: HMC_BOUNDARY(HMC_MOORE26) break;
+    }
+#undef HMC_BOUNDARY
     HMC_HIP(hipGetLastError());
     return HMC_OK;
 }

@@ -280,6 +280,7 @@ uint32_t philox_u32(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag) {
 
 struct hmc_mlp_s {
     hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;     // orders work on other streams after the handle's own
     DevBuf theta, m, v;
     int64_t step = 0;
     double mean = 0.0, sdev = 1.0;
@@ -368,6 +369,7 @@ hmc_status hmc_mlp_free(hmc_mlp* M) {
     for (DevBuf* b : {&M->theta, &M->m, &M->v, &M->X, &M->t, &M->partial, &M->sel, &M->loss, &M->grad, &M->euler,
                       &M->eps, &M->E, &M->Eaudit, &M->Bq, &M->audit_idx})
         b->release();
+    if (M->ready) (void)hipEventDestroy(M->ready);
     (void)hipStreamDestroy(M->stream);
     delete M;
     return HMC_OK;
@@ -560,6 +562,24 @@ hmc_status hmc_mlp_forward(hmc_mlp* M, const float* X, int32_t n, float* y_out) 
     HMC_HIP(hipGetLastError());
     HMC_HIP(hipMemcpyAsync(y_out, M->t.p, (size_t)n * 4, hipMemcpyDeviceToHost, M->stream));
     HMC_HIP(hipStreamSynchronize(M->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_mlp_infer(hmc_mlp* M, const float* X_dev, float* y_dev, int64_t n, void* stream) {
+    set_error("");
+    if (!M || !X_dev || !y_dev || n < 0) return fail(HMC_E_INVAL, "NULL argument or n < 0");
+    if (n >= (int64_t)1 << 40) return fail(HMC_E_INVAL, "n too large");
+    if (n == 0) return HMC_OK;
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : M->stream;
+    if (s != M->stream) {
+        // the parameters may still be in flight on the handle's stream
+        if (!M->ready) HMC_HIP(hipEventCreateWithFlags(&M->ready, hipEventDisableTiming));
+        HMC_HIP(hipEventRecord(M->ready, M->stream));
+        HMC_HIP(hipStreamWaitEvent(s, M->ready, 0));
+    }
+    predict_kernel<<<(unsigned)((n + kPredThreads - 1) / kPredThreads), kPredThreads, 0, s>>>(
+        M->theta.as<float>(), X_dev, n, 0.0, 1.0, nullptr, y_dev);
+    HMC_HIP(hipGetLastError());
     return HMC_OK;
 }
 

@@ -193,13 +193,15 @@ void destroy(hmc_lattice* L) {
     if (!L) return;
     if (L->stream) (void)hipStreamSynchronize(L->stream);
     const size_t sb = (size_t)L->N * L->spin_bytes;
-    dev_free(L->spins[0], sb);
+    if (!L->borrowed) dev_free(L->spins[0], sb);
     dev_free(L->spins[1], sb);
     dev_free(L->snap, sb);
     dev_free(L->dB, (size_t)L->Q * 4);
     dev_free(L->d_areas, (size_t)L->Q * 4);
     dev_free(L->d_stats, (size_t)(1 + L->stats_bins_cap) * 8);
     dev_free(L->d_gbin, (size_t)L->Q * 4);
+    dev_free(L->d_trials, kTrialSlots * sizeof(unsigned long long));
+    dev_free(L->d_count, sizeof(unsigned long long));
     free_table(L->table);
     for (auto& e : L->events) {
         (void)hipEventDestroy(e.first);
@@ -209,7 +211,8 @@ void destroy(hmc_lattice* L) {
     delete L;
 }
 
-hmc_status create(const hmc_lattice_desc* d, int32_t n_grains, void* stream, hmc_lattice** out) {
+hmc_status create(const hmc_lattice_desc* d, int32_t n_grains, void* stream, hmc_lattice** out,
+                  void* borrowed_spins = nullptr) {
     if (!out) return fail(HMC_E_INVAL, "out is NULL");
     *out = nullptr;
     HMC_TRY(validate_desc(d, n_grains));
@@ -236,7 +239,12 @@ hmc_status create(const hmc_lattice_desc* d, int32_t n_grains, void* stream, hmc
         L->own_stream = true;
     }
     const size_t sb = (size_t)L->N * L->spin_bytes;
-    if (st == HMC_OK) st = dev_alloc(&L->spins[0], sb, "spins");
+    if (borrowed_spins) {
+        L->spins[0] = borrowed_spins;
+        L->borrowed = true;
+    } else if (st == HMC_OK) {
+        st = dev_alloc(&L->spins[0], sb, "spins");
+    }
     if (st == HMC_OK) st = dev_alloc(&L->spins[1], sb, "spins (second buffer)");
     if (st == HMC_OK) st = dev_alloc(reinterpret_cast<void**>(&L->dB), (size_t)L->Q * 4, "grain energies");
     if (st == HMC_OK) st = dev_alloc(reinterpret_cast<void**>(&L->d_areas), (size_t)L->Q * 4, "grain areas");
@@ -246,7 +254,7 @@ hmc_status create(const hmc_lattice_desc* d, int32_t n_grains, void* stream, hmc
         st = dev_alloc(reinterpret_cast<void**>(&L->d_stats), (size_t)(1 + L->stats_bins_cap) * 8, "stats");
     }
     if (st == HMC_OK) {
-        e = hipMemsetAsync(L->spins[0], 0, sb, L->stream);
+        e = L->borrowed ? hipSuccess : hipMemsetAsync(L->spins[0], 0, sb, L->stream);
         if (e == hipSuccess) e = hipMemsetAsync(L->dB, 0, (size_t)L->Q * 4, L->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
         if (e != hipSuccess) st = hip_fail(e, "lattice set-up");
@@ -268,7 +276,7 @@ using namespace hmc;
 
 extern "C" {
 
-int32_t hmc_abi_version(void) { return 1; }
+int32_t hmc_abi_version(void) { return 2; }
 
 const char* hmc_last_error(void) { return g_error.c_str(); }
 
@@ -296,6 +304,43 @@ hmc_status hmc_lattice_init(const hmc_lattice_desc* desc, int32_t n_grains, uint
     }
     *out = L;
     return HMC_OK;
+}
+
+hmc_status hmc_lattice_wrap(const hmc_lattice_desc* desc, void* dev_spins, int32_t n_grains, void* stream,
+                            hmc_lattice** out) {
+    g_error.clear();
+    if (!dev_spins) {
+        if (out) *out = nullptr;
+        return fail(HMC_E_INVAL, "dev_spins is NULL");
+    }
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, dev_spins) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        if (out) *out = nullptr;
+        return fail(HMC_E_INVAL, "dev_spins is not device memory");
+    }
+    if (desc && desc->dims[0] > 0 && desc->dims[1] > 0) {
+        // the allocation holding dev_spins must cover the whole lattice
+        const uint64_t n = (uint64_t)desc->dims[0] * desc->dims[1] * (desc->ndim == 3 ? (uint64_t)desc->dims[2] : 1u);
+        const uint64_t bytes = n * (desc->spin == HMC_I16 ? 2u : 4u);
+        const uint64_t align = desc->spin == HMC_I16 ? 2u : 4u;
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)dev_spins) == hipSuccess) {
+            const uint64_t off = (uint64_t)((char*)dev_spins - (char*)base);
+            if (off + bytes > size) {
+                if (out) *out = nullptr;
+                return fail(HMC_E_INVAL, "dev_spins allocation is smaller than the lattice");
+            }
+        } else {
+            (void)hipGetLastError();
+        }
+        if ((uintptr_t)dev_spins % align) {
+            if (out) *out = nullptr;
+            return fail(HMC_E_INVAL, "dev_spins is not aligned to the spin size");
+        }
+    }
+    return create(desc, n_grains, stream, out, dev_spins);
 }
 
 hmc_status hmc_lattice_free(hmc_lattice* L) {
@@ -472,7 +517,41 @@ hmc_status hmc_get_tiling(const hmc_lattice* L, int32_t* out4) {
 hmc_status hmc_profile(hmc_lattice* L, int32_t enable) {
     g_error.clear();
     if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (enable && !L->d_trials) {
+        HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_trials), kTrialSlots * sizeof(unsigned long long),
+                          "trial counters"));
+        HMC_HIP(hipMemsetAsync(L->d_trials, 0, kTrialSlots * sizeof(unsigned long long), L->stream));
+    }
     L->profiling = enable != 0;
+    return HMC_OK;
+}
+
+hmc_status hmc_profile_trials(hmc_lattice* L, int64_t* trials) {
+    g_error.clear();
+    if (!L || !trials) return fail(HMC_E_INVAL, "NULL argument");
+    *trials = 0;
+    if (!L->d_trials) return HMC_OK;
+    std::vector<unsigned long long> h(kTrialSlots);
+    HMC_HIP(hipMemcpyAsync(h.data(), L->d_trials, kTrialSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           L->stream));
+    HMC_HIP(hipMemsetAsync(L->d_trials, 0, kTrialSlots * sizeof(unsigned long long), L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    unsigned long long total = 0;
+    for (unsigned long long v : h) total += v;
+    *trials = (int64_t)total;
+    return HMC_OK;
+}
+
+hmc_status hmc_boundary_sites(hmc_lattice* L, int64_t* n_out) {
+    g_error.clear();
+    if (!L || !n_out) return fail(HMC_E_INVAL, "NULL argument");
+    if (!L->d_count)
+        HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_count), sizeof(unsigned long long), "boundary count"));
+    HMC_TRY(launch_boundary_count(L));
+    unsigned long long h = 0;
+    HMC_HIP(hipMemcpyAsync(&h, L->d_count, sizeof(h), hipMemcpyDeviceToHost, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    *n_out = (int64_t)h;
     return HMC_OK;
 }
 

@@ -74,6 +74,7 @@ struct LatArgs {
     int32_t nb, nbound;       // buckets per row, bound pairs in total
     uint32_t bw, m_bw;        // bucket width and its reciprocal (m_bw = 0: divide)
     uint32_t uniform;         // 1: symmetric trial spins
+    unsigned long long* trials;   // when not null: kTrialSlots counters of Philox draws (queued trials)
 };
 
 // Per-launch arguments: the LDS box and its precomputed reciprocals.
@@ -216,6 +217,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     const uint32_t px = (uint32_t)(x0 & 1), py = (uint32_t)(y0 & 1), pz = (uint32_t)(z0 & 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
 
+    unsigned long long drawn = 0;   // queued trials of this tile (thread 0; profiling only)
     for (uint32_t pass = 0; pass < g.P; ++pass) {
         const uint32_t c = pass % C;
         const uint32_t t = a.t0 + pass / C;
@@ -386,7 +388,10 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         }
         __syncthreads();
         const uint32_t count = *qc;
-        if (tid == 0) qcount[(pass + 1) & 1] = 0;
+        if (tid == 0) {
+            qcount[(pass + 1) & 1] = 0;
+            drawn += count;
+        }
         for (uint32_t e0 = tid; e0 < count; e0 += 2 * nthr) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -396,6 +401,9 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         }
         __syncthreads();
     }
+
+    // one counter update per tile, spread over kTrialSlots addresses
+    if (a.trials && tid == 0) atomicAdd(&a.trials[blockIdx.x & (kTrialSlots - 1)], drawn);
 
     // Interior back to global memory: flat over the tile, coalesced rows.
     const uint32_t tile_n = a.TX * a.TY * a.TZ;
@@ -582,6 +590,7 @@ LatArgs lat_args(const hmc_lattice* L, const Tiling& t, uint64_t seed) {
     if (a.bw == 1) a.m_bw = 1u;
     else a.m_bw = (uint64_t)L->table.TW * (uint64_t)a.bw < (1ull << 32) ? magic(a.bw) : 0u;
     a.uniform = L->desc.proposal == HMC_PROP_UNIFORM ? 1u : 0u;
+    a.trials = L->profiling ? L->d_trials : nullptr;
     return a;
 }
 
@@ -609,12 +618,20 @@ hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t max
     return HMC_OK;
 }
 
-void default_tiling(int nbr, int& tile2, int& tile3, int& k) {
+// Default tilings in order of preference (measured on the 1024^2 VN4 and
+// 256^3 VN6 workloads); the first that fits the LDS after each side is cut to
+// an even divisor of the lattice side is used.
+std::vector<Tiling> default_tilings(int nbr) {
+    auto T = [](int x, int y, int z, int k) {
+        Tiling t;
+        t.tx = x; t.ty = y; t.tz = z; t.k = k;
+        return t;
+    };
     switch (nbr) {
-    case HMC_VN4: tile2 = 64; tile3 = 16; k = 4; break;
-    case HMC_MOORE8: tile2 = 64; tile3 = 16; k = 2; break;
-    case HMC_VN6: tile2 = 64; tile3 = 16; k = 1; break;
-    default: tile2 = 64; tile3 = 8; k = 1; break;
+    case HMC_VN4: return {T(64, 64, 1, 4), T(32, 32, 1, 4), T(16, 16, 1, 2)};
+    case HMC_MOORE8: return {T(64, 64, 1, 2), T(32, 32, 1, 2), T(16, 16, 1, 1)};
+    case HMC_VN6: return {T(32, 32, 16, 1), T(32, 16, 16, 1), T(16, 16, 16, 1), T(8, 8, 8, 1)};
+    default: return {T(8, 8, 8, 1), T(4, 4, 4, 1)};
     }
 }
 
@@ -626,7 +643,7 @@ int lds_limit_bytes() {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            cached = std::min(v, 65536);
+            cached = v;
         else
             cached = 65536;
     }
@@ -637,21 +654,35 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
     const int* dims = L->desc.dims;
     Tiling r = t;
     if (!explicit_request || r.tx == 0 || r.ty == 0 || (L->ndim == 3 && r.tz == 0) || r.k == 0) {
-        int tile2, tile3, k;
-        default_tiling(L->desc.nbr, tile2, tile3, k);
         const Tiling* tuned = tuned_tiling(L->desc, L->Q);
         if (tuned && r.tx == 0 && r.ty == 0 && r.tz == 0 && r.k == 0) {
             r = *tuned;
         } else {
-            if (r.tx == 0) r.tx = largest_even_divisor_at_most(dims[0], L->ndim == 2 ? tile2 : tile3);
-            if (r.ty == 0) r.ty = largest_even_divisor_at_most(dims[1], L->ndim == 2 ? tile2 : tile3);
-            if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], tile3);
-            if (r.k == 0) r.k = k;
+            const Tiling req = r;
+            for (const Tiling& d : default_tilings(L->desc.nbr)) {
+                r = req;
+                if (r.tx == 0) r.tx = largest_even_divisor_at_most(dims[0], d.tx);
+                if (r.ty == 0) r.ty = largest_even_divisor_at_most(dims[1], d.ty);
+                if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], d.tz);
+                if (L->ndim == 2) r.tz = 1;
+                if (r.k == 0) r.k = d.k;
+                const Layout lay = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, r.k * L->C);
+                if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
+            }
         }
     }
     if (L->ndim == 2) r.tz = 1;
     HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, L->Q, dims, r));
     t = r;
+    return HMC_OK;
+}
+
+// A lattice over a caller's buffer keeps its state there between calls.
+hmc_status settle_borrowed(hmc_lattice* L) {
+    if (!L->borrowed || L->cur == 0) return HMC_OK;
+    HMC_HIP(hipMemcpyAsync(L->spins[0], L->spins[1], (size_t)L->N * L->spin_bytes, hipMemcpyDeviceToDevice,
+                           L->stream));
+    L->cur = 0;
     return HMC_OK;
 }
 
@@ -667,10 +698,18 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     const uint32_t ntiles = a.ntx * a.nty * (a.Lz / a.TZ);
     const uint32_t xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
 
-    int32_t remaining = n_mcs;
+    // MC steps per launch.  A borrowed spin buffer must hold the result: when
+    // the launch count would leave it in the second buffer, the last launch
+    // is split in two (results do not depend on the split).
+    std::vector<int> chunks;
+    for (int32_t rem = n_mcs; rem > 0; rem -= std::min<int32_t>(t.k, rem)) chunks.push_back(std::min<int32_t>(t.k, rem));
+    if (L->borrowed && ((L->cur + (int)chunks.size()) & 1) && !chunks.empty() && chunks.back() >= 2) {
+        const int kl = chunks.back();
+        chunks.back() = kl / 2;
+        chunks.push_back(kl - kl / 2);
+    }
     uint64_t t_next = L->mcs;
-    while (remaining > 0) {
-        const int k = std::min<int32_t>(t.k, remaining);
+    for (const int k : chunks) {
         const int passes = k * L->C;
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
@@ -700,10 +739,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         }
         L->cur ^= 1;
         t_next += (uint64_t)k;
-        remaining -= k;
     }
     L->mcs += (uint64_t)n_mcs;
-    return HMC_OK;
+    return settle_borrowed(L);
 }
 
 // ------------------------------------------------------------------ ensemble
@@ -718,13 +756,15 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
     }
     E->maxQ = maxQ;
     if (E->tiling.tx == 0 || E->tiling.k == 0) {
-        int tile2, tile3, k;
-        default_tiling(L0->desc.nbr, tile2, tile3, k);
         Tiling t;
-        t.tx = largest_even_divisor_at_most(g[0], L0->ndim == 2 ? tile2 : tile3);
-        t.ty = largest_even_divisor_at_most(g[1], L0->ndim == 2 ? tile2 : tile3);
-        t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], tile3) : 1;
-        t.k = k;
+        for (const Tiling& d : default_tilings(L0->desc.nbr)) {
+            t.tx = largest_even_divisor_at_most(g[0], d.tx);
+            t.ty = largest_even_divisor_at_most(g[1], d.ty);
+            t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], d.tz) : 1;
+            t.k = d.k;
+            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, t, t.k * L0->C);
+            if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
+        }
         E->tiling = t;
     }
     for (hmc_lattice* L : E->lats)
@@ -751,7 +791,9 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C);
-    const int per_cu = std::max(1, std::min(2, (int)(lds_limit_bytes() * 2 / std::max<size_t>(lay.bytes, 1))));
+    // resident workgroups per CU: two 1024-thread groups fill the wave slots;
+    // the LDS of a CU (equal to the per-group limit on gfx950) may allow fewer
+    const int per_cu = std::max(1, std::min(2, (int)(lds_limit_bytes() / std::max<size_t>(lay.bytes, 1))));
     E->grid = std::max(1u, std::min(E->ntiles, (uint32_t)(cus * per_cu)));
     for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
     E->graphs.clear();
@@ -775,6 +817,7 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         HMC_TRY(build_table(L->table, kT[i], L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
         if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
         h[i].a = lat_args(L, E->tiling, seed[i]);
+        h[i].a.trials = nullptr;
         h[i].buf[0] = L->spins[0];
         h[i].buf[1] = L->spins[1];
         h[i].cur = (uint32_t)L->cur;
@@ -826,6 +869,7 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         HMC_HIP(hipStreamWaitEvent(L->stream, E->ev, 0));
         L->cur ^= (int)(launches & 1u);
         L->mcs += (uint64_t)n_mcs;
+        HMC_TRY(settle_borrowed(L));
     }
     return HMC_OK;
 }

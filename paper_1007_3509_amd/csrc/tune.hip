@@ -37,7 +37,7 @@ std::vector<Tiling> candidates(const hmc_lattice_desc& d) {
     std::vector<Tiling> out;
     const int C = nbr_info(d.nbr).C;
     const std::vector<int> sides2 = {16, 32, 64, 128, 256};
-    const std::vector<int> sides3 = {4, 8, 16, 32};
+    const std::vector<int> sides3 = {4, 8, 16, 32, 64};
     const std::vector<int> ks = {1, 2, 4, 8};
     auto divides = [&](int s, int L) { return s <= L && L % s == 0; };
     if (d.ndim == 2) {

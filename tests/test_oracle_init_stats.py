@@ -97,3 +97,59 @@ def test_sweep_rejects_bad_arguments(orc):
         orc.sweep(s, 0, (4, 4), [0], 1.0, -1, 1)
     with pytest.raises(ValueError):   # energy change leaves int32
         orc.sweep(np.array([[0, 1, 0, 1]] * 4, np.int32), 0, (4, 4), [-2 ** 31, 2 ** 31 - 1], 1.0, 1, 1)
+
+
+# ------------------------------------------------------- boundary sites
+
+def _brute_boundary(s, offs, Q):
+    """Pure-Python loops over every site and every neighbour offset."""
+    shape = s.shape
+    n = 0
+    for idx in np.ndindex(*shape):
+        q = s[idx]
+        if not 0 <= q < Q:
+            continue
+        for o in offs:
+            j = tuple((idx[a] + o[a]) % shape[a] for a in range(len(shape)))
+            if s[j] != q:
+                n += 1
+                break
+    return n
+
+
+def test_boundary_sites_closed_forms(orc):
+    # uniform lattice: none; 2-colour checkerboard under VN4: every site
+    assert orc.boundary_sites(np.zeros((8, 6), np.int32), orc.VN4, (6, 8), 2) == 0
+    yy, xx = np.mgrid[0:8, 0:6]
+    cb = ((xx + yy) & 1).astype(np.int32)
+    assert orc.boundary_sites(cb, orc.VN4, (6, 8), 2) == 48
+    assert orc.boundary_sites(cb, orc.MOORE8, (6, 8), 2) == 48
+    # a strip of rows across x has two flat interfaces: one row on each side
+    # of each is a boundary row, for VN4 and Moore8 alike (4 Lx sites)
+    st = np.zeros((16, 10), np.int32)
+    st[5:11, :] = 1
+    for nbr in (orc.VN4, orc.MOORE8):
+        assert orc.boundary_sites(st, nbr, (10, 16), 2) == 4 * 10
+    # a slab of planes in 3D: four boundary planes
+    sl = np.zeros((8, 6, 4), np.int32)
+    sl[2:5] = 1
+    for nbr in (orc.VN6, orc.MOORE26):
+        assert orc.boundary_sites(sl, nbr, (4, 6, 8), 2) == 4 * 4 * 6
+    # values outside [0, Q) are not counted (but still differ from neighbours)
+    st2 = st.copy()
+    st2[0, 0] = -1
+    assert orc.boundary_sites(st2, orc.VN4, (10, 16), 2) == 4 * 10 + 4   # its 4 neighbours join
+
+
+@pytest.mark.parametrize("nbr,shape", [(0, (6, 8)), (1, (8, 6)), (2, (4, 6, 4)), (3, (4, 4, 6))])
+def test_boundary_sites_brute_force(orc, nbr, shape):
+    rng = np.random.default_rng(nbr + 10)
+    s = rng.integers(0, 3, size=shape).astype(np.int32)
+    s[rng.random(shape) < 0.5] = 0
+    dims = tuple(reversed(shape))
+    offs2 = {0: [(0, 1), (0, -1), (1, 0), (-1, 0)],
+             1: [(a, b) for a in (-1, 0, 1) for b in (-1, 0, 1) if (a, b) != (0, 0)]}
+    offs3 = {2: [(0, 0, 1), (0, 0, -1), (0, 1, 0), (0, -1, 0), (1, 0, 0), (-1, 0, 0)],
+             3: [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]}
+    offs = offs2.get(nbr) or offs3[nbr]
+    assert orc.boundary_sites(s, nbr, dims, 3) == _brute_boundary(s, offs, 3)
