@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_HBM_GBPS = 8000.0
+VALU_ISSUE_PER_S = 256 * 2.4e9      # wave64 VALU instructions per second, whole chip
 WORKLOADS = {
     "voronoi_2d_64": synth.voronoi_2d_64,
     "schmid_2d_1024": synth.schmid_2d_1024,
@@ -60,26 +61,26 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload, tiling):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when the kernel source or the tiling changed since it was taken."""
+def measured_profile(workload, tiling):
+    """Per-launch figures of the sweep kernel from the committed rocprofv3
+    summary (scaled HBM bytes, VALU wave instructions), or {} when the kernel
+    source or the tiling changed since they were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"sweep_tile_kernel_{workload}.md")
     src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "sweep.hip")
     if not os.path.exists(path):
-        return None
+        return {}
+    keys = ("traffic_bytes_per_launch", "valu_wave_instructions_per_launch", "kernel_source_sha256", "tiling")
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "tiling"):
+        if ":" in line and line.split(":")[0] in keys:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
-        return None
-    if fields.get("tiling") != ",".join(str(v) for v in tiling):
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    if fields.get("kernel_source_sha256") != sha or fields.get("tiling") != ",".join(str(v) for v in tiling):
+        return {}
+    return {k: float(fields[k]) for k in keys[:2] if k in fields}
 
 
 def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
@@ -182,7 +183,9 @@ def main():
     su_per_launch = su / max(launches, 1)
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
     tiling = lat.tiling()
-    traffic = measured_traffic(w.name, tiling)
+    prof = measured_profile(w.name, tiling)
+    traffic = prof.get("traffic_bytes_per_launch")
+    valu = prof.get("valu_wave_instructions_per_launch")
 
     out = {
         "metric": "Potts site-updates/s (HBM GB/s vs peak in roofline), 1 MI355X, bit-exact vs oracle",
@@ -225,6 +228,14 @@ def main():
             "boundary_site_fraction": {"start": fb_start, "end": fb_end},
             "work_note": "Philox calls = queued trials including the redundant halo work of fused steps; "
                          "boundary fraction = sites with an unlike neighbour / N",
+            "traffic_gbps": traffic / avg_launch_s / 1e9 if traffic else None,
+            "valu": {
+                "wave_instructions_per_launch": valu,
+                "per_site_update": valu / su_per_launch if valu else None,
+                "issue_frac": valu / (avg_launch_s * VALU_ISSUE_PER_S) if valu else None,
+                "note": "SQ_INSTS_VALU from profiles/ (null if the kernel changed) against 256 CUs x 2.4 GHz x "
+                        "1 VALU wave instruction per CU per cycle: the resource that binds this kernel",
+            },
         },
         "final_grains": stats[0],
         "final_mean_area": stats[1],
