@@ -80,10 +80,13 @@ struct LatArgs {
 // Per-launch arguments: the LDS box and its precomputed reciprocals.
 struct RunArgs {
     uint32_t BX, BY, BZ;      // LDS box (BZ = 1 in 2D)
-    uint32_t H;               // halo per side (= passes of this launch)
+    uint32_t H;               // halo per side (= passes of this launch) along y and z
+    uint32_t HX;              // halo along x: H, or H rounded up to 4 for 8-byte row access
+    uint32_t vec;             // 1: stage and store 16-bit spins four at a time (8-byte aligned)
     uint32_t P;               // passes in this launch
     uint32_t box_off, queue_off, coord_off, grain_off;   // byte offsets in dynamic LDS
     uint32_t m_bx, m_by, m_tx, m_ty;
+    uint32_t m_bx4, m_tx4;    // reciprocals of BX / 4 and TX / 4 (vec)
     uint32_t m_pass[kMaxPasses][2];   // per pass: per-row and rows reciprocals
 };
 
@@ -176,7 +179,8 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 
     const uint32_t H = g.H;
     const uint32_t Hz = (D == 3) ? H : 0u;
-    const int64_t x0 = (int64_t)tx * a.TX - (int64_t)H;
+    const uint32_t HX = g.HX;
+    const int64_t x0 = (int64_t)tx * a.TX - (int64_t)HX;
     const int64_t y0 = (int64_t)ty * a.TY - (int64_t)H;
     const int64_t z0 = (int64_t)tz * a.TZ - (int64_t)Hz;
     for (uint32_t u = tid; u < g.BX; u += nthr) gxs[u] = wrap_coord(x0 + u, a.Lx);
@@ -188,7 +192,34 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     if (tid < 2) qcount[tid] = 0;
     __syncthreads();
     const uint32_t box_n = g.BX * g.BY * g.BZ;
-    for (uint32_t e0 = tid; e0 < box_n; e0 += kUnroll * nthr) {
+    bool staged = false;
+    if constexpr (sizeof(Spin) == 2) {
+        if (g.vec) {
+            // four spins per 8-byte load: box rows start at a global x that is a
+            // multiple of 4 and Lx is a multiple of 4, so a group never wraps
+            const uint32_t bx4 = g.BX >> 2, groups = box_n >> 2;
+            for (uint32_t e0 = tid; e0 < groups; e0 += kUnroll * nthr) {
+                uint64_t v[kUnroll];
+#pragma unroll
+                for (int j = 0; j < kUnroll; ++j) {
+                    const uint32_t e = e0 + j * nthr;
+                    const uint32_t ec = e < groups ? e : 0u;
+                    const uint32_t r = fdiv(ec, g.m_bx4);
+                    const uint32_t u4 = ec - __umul24(r, bx4);
+                    const uint32_t w = (D == 3) ? fdiv(r, g.m_by) : 0u;
+                    const uint32_t vv = r - __umul24(w, g.BY);
+                    v[j] = *reinterpret_cast<const uint64_t*>(src + gxs[4 * u4] + a.Lx * (gys[vv] + a.Ly * gzs[w]));
+                }
+#pragma unroll
+                for (int j = 0; j < kUnroll; ++j) {
+                    const uint32_t e = e0 + j * nthr;
+                    if (e < groups) *reinterpret_cast<uint64_t*>(box + 4 * e) = v[j];
+                }
+            }
+            staged = true;
+        }
+    }
+    for (uint32_t e0 = tid; !staged && e0 < box_n; e0 += kUnroll * nthr) {
         int32_t v[kUnroll];
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
@@ -222,8 +253,9 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
         const uint32_t c = pass % C;
         const uint32_t t = a.t0 + pass / C;
         const uint32_t lo = pass + 1;
+        const uint32_t lox = lo + (HX - H);   // the same ring counted from the padded x edge
         const uint32_t loz = (D == 3) ? lo : 0;
-        const uint32_t Wx = g.BX - 2 * lo;
+        const uint32_t Wx = g.BX - 2 * lox;
         const uint32_t Wy = g.BY - 2 * lo;
         const uint32_t Wz = (D == 3) ? g.BZ - 2 * lo : 1;
         // colour-class enumeration: sites per row, rows per plane, planes
@@ -290,7 +322,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             // Checkerboard, 16-bit spins: a lane takes 4 consecutive sites of a
             // row as one 64-bit word, XORs it with its four (six) neighbour
             // words and tests the two colour-c fields.
-            const uint32_t s_lo = lo >> 2, s_hi = (g.BX - lo - 1) >> 2;
+            const uint32_t s_lo = lox >> 2, s_hi = (g.BX - lox - 1) >> 2;
             const uint32_t nseg = s_hi - s_lo + 1;
             const uint32_t totalS = nseg * Wy * Wz;
             const uint32_t plane = g.BX * g.BY;
@@ -325,8 +357,8 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     }
                     const uint32_t k = (c ^ (v + w + pbase)) & 1u;   // first colour-c field
                     const uint32_t ua = u0 + k, ub = u0 + k + 2;
-                    pa = ua >= lo && ua < g.BX - lo && ((x >> (16 * k)) & 0xFFFFull) != 0;
-                    pb = ub >= lo && ub < g.BX - lo && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
+                    pa = ua >= lox && ua < g.BX - lox && ((x >> (16 * k)) & 0xFFFFull) != 0;
+                    pb = ub >= lox && ub < g.BX - lox && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
                     qa = ua | (v << 10) | (w << 20);
                     qb = ub | (v << 10) | (w << 20);
                 }
@@ -358,10 +390,10 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                         if (kCheckerboard) {
                             v = lo + ri;
                             w = loz + pl;
-                            const uint32_t par = (lo + v + w + px + py + pz) & 1u;
-                            u = lo + 2 * jj + ((c ^ par) & 1u);
+                            const uint32_t par = (lox + v + w + px + py + pz) & 1u;
+                            u = lox + 2 * jj + ((c ^ par) & 1u);
                         } else {
-                            u = lo + 2 * jj + ((cx ^ (lo + px)) & 1u);
+                            u = lox + 2 * jj + ((cx ^ (lox + px)) & 1u);
                             v = lo + 2 * ri + ((cy ^ (lo + py)) & 1u);
                             w = (D == 3) ? lo + 2 * pl + ((cz ^ (lo + pz)) & 1u) : 0u;
                         }
@@ -407,13 +439,28 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 
     // Interior back to global memory: flat over the tile, coalesced rows.
     const uint32_t tile_n = a.TX * a.TY * a.TZ;
-    const uint32_t gx0 = gxs[H];
+    const uint32_t gx0 = gxs[HX];
+    if constexpr (sizeof(Spin) == 2) {
+        if (g.vec) {
+            const uint32_t tx4 = a.TX >> 2, groups = tile_n >> 2;
+            for (uint32_t e = tid; e < groups; e += nthr) {
+                const uint32_t r = fdiv(e, g.m_tx4);
+                const uint32_t u4 = e - __umul24(r, tx4);
+                const uint32_t w = (D == 3) ? fdiv(r, g.m_ty) : 0u;
+                const uint32_t vv = r - __umul24(w, a.TY);
+                const uint64_t val =
+                    *reinterpret_cast<const uint64_t*>(box + (HX + 4 * u4) + __umul24(g.BX, (H + vv) + __umul24(g.BY, Hz + w)));
+                *reinterpret_cast<uint64_t*>(dst + gx0 + 4 * u4 + a.Lx * (gys[H + vv] + a.Ly * gzs[Hz + w])) = val;
+            }
+            return;
+        }
+    }
     for (uint32_t e = tid; e < tile_n; e += nthr) {
         const uint32_t r = fdiv(e, g.m_tx);
         const uint32_t u = e - __umul24(r, a.TX);
         const uint32_t w = (D == 3) ? fdiv(r, g.m_ty) : 0u;
         const uint32_t vv = r - __umul24(w, a.TY);
-        const Spin val = box[(H + u) + __umul24(g.BX, (H + vv) + __umul24(g.BY, Hz + w))];
+        const Spin val = box[(HX + u) + __umul24(g.BX, (H + vv) + __umul24(g.BY, Hz + w))];
         dst[gx0 + u + a.Lx * (gys[H + vv] + a.Ly * gzs[Hz + w])] = val;
     }
 }
@@ -496,13 +543,17 @@ struct Layout {
     uint32_t BX, BY, BZ, H;
     size_t box_off, queue_off, coord_off, grain_off, bytes;
     bool grains_in_lds;
+    uint32_t HX;              // x halo (H, or H rounded up to 4 with vec)
+    bool vec;                 // 8-byte staging and store of 16-bit spins
 };
 
 // LDS layout of one tile: [bucket bounds, queue counters | box | queue | coords | grains].
-Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes) {
+Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes, bool vec) {
     Layout o{};
     o.H = (uint32_t)passes;
-    o.BX = (uint32_t)(t.tx + 2 * passes);
+    o.HX = vec ? (uint32_t)((passes + 3) & ~3) : (uint32_t)passes;
+    o.vec = vec;
+    o.BX = (uint32_t)(t.tx + 2 * o.HX);
     o.BY = (uint32_t)(t.ty + 2 * passes);
     o.BZ = ndim == 3 ? (uint32_t)(t.tz + 2 * passes) : 1u;
     const size_t elems = (size_t)o.BX * o.BY * o.BZ;
@@ -526,14 +577,31 @@ Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tili
     return o;
 }
 
+// Four 16-bit spins per 8-byte access along x: needs checkerboard int16
+// lattices whose tiles and x side are multiples of 4 and 8-byte aligned
+// spin buffers (a borrowed buffer may be aligned to 2 bytes only).
+bool vec_ok(const hmc_lattice* L, const Tiling& t) {
+    return L->desc.spin == HMC_I16 && (L->desc.nbr == HMC_VN4 || L->desc.nbr == HMC_VN6) && t.tx % 4 == 0 &&
+           L->desc.dims[0] % 4 == 0 && reinterpret_cast<uintptr_t>(L->spins[0]) % 8 == 0 &&
+           reinterpret_cast<uintptr_t>(L->spins[1]) % 8 == 0;
+}
+
 Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
-    return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes);
+    if (vec_ok(L, t)) {
+        const Layout v = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, true);
+        if ((int64_t)v.bytes <= lds_limit_bytes() && v.BX <= 1023) return v;
+    }
+    return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, false);
 }
 
 RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool swar) {
     RunArgs g{};
     g.BX = lay.BX; g.BY = lay.BY; g.BZ = lay.BZ;
     g.H = lay.H;
+    g.HX = lay.HX;
+    g.vec = lay.vec ? 1u : 0u;
+    g.m_bx4 = magic(lay.BX / 4);
+    g.m_tx4 = magic((uint32_t)t.tx / 4);
     g.P = (uint32_t)passes;
     g.box_off = (uint32_t)lay.box_off;
     g.queue_off = (uint32_t)lay.queue_off;
@@ -546,9 +614,10 @@ RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool s
     const bool cb = nbr == HMC_VN4 || nbr == HMC_VN6;
     for (int ps = 0; ps < passes; ++ps) {
         const uint32_t lo = (uint32_t)ps + 1;
-        const uint32_t Wx = lay.BX - 2 * lo, Wy = lay.BY - 2 * lo;
+        const uint32_t lox = lo + (lay.HX - lay.H);
+        const uint32_t Wx = lay.BX - 2 * lox, Wy = lay.BY - 2 * lo;
         if (swar) {   // rows of 4-site segments
-            const uint32_t nseg = ((lay.BX - lo - 1) >> 2) - (lo >> 2) + 1;
+            const uint32_t nseg = ((lay.BX - lox - 1) >> 2) - (lox >> 2) + 1;
             g.m_pass[ps][0] = magic(nseg);
             g.m_pass[ps][1] = magic(Wy);
         } else {
@@ -609,7 +678,7 @@ hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t max
     }
     if (r.k < 1 || r.k * C > kMaxPasses)
         return fail(HMC_E_INVAL, "mcs_per_launch * colours must be in [1, " + std::to_string(kMaxPasses) + "]");
-    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, r.k * C);
+    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, r.k * C, false);
     if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
         return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
     if ((int64_t)lay.bytes > lds_limit_bytes())
@@ -666,7 +735,7 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
                 if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], d.tz);
                 if (L->ndim == 2) r.tz = 1;
                 if (r.k == 0) r.k = d.k;
-                const Layout lay = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, r.k * L->C);
+                const Layout lay = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, r.k * L->C, false);
                 if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
             }
         }
@@ -762,7 +831,7 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
             t.ty = largest_even_divisor_at_most(g[1], d.ty);
             t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], d.tz) : 1;
             t.k = d.k;
-            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, t, t.k * L0->C);
+            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, t, t.k * L0->C, false);
             if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
         }
         E->tiling = t;
@@ -790,7 +859,7 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C);
+    const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C, false);
     // resident workgroups per CU: two 1024-thread groups fill the wave slots;
     // the LDS of a CU (equal to the per-group limit on gfx950) may allow fewer
     const int per_cu = std::max(1, std::min(2, (int)(lds_limit_bytes() / std::max<size_t>(lay.bytes, 1))));
@@ -837,7 +906,7 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         while (remaining > 0 && err == hipSuccess) {
             const int k = std::min<int32_t>(E->tiling.k, remaining);
             const int passes = k * C;
-            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes);
+            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes, false);
             const bool swar = use_swar(L0->desc.nbr, L0->desc.spin, lay.BX);
             RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes, swar);
             const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true, swar);
