@@ -232,3 +232,17 @@ def test_moore8_member_full_1000_mcs():
                          vseed=w.voronoi_seed)
     want = oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, w.n_mcs, w.sweep_seed, threads=THREADS)
     assert_same(got, want, w.name)
+
+
+# ------------------------------------------------ grain-energy placement
+
+@pytest.mark.parametrize("Q,spread", [(5000, 0.9), (50, 3.0), (7, 0.0)])
+def test_grain_energy_placement(Q, spread):
+    # spread < 1 (2^16 fixed-point units): energies staged in LDS as 16-bit
+    # offsets; wider spreads are read from global memory; both exact
+    rng = np.random.default_rng(Q)
+    B = synth.quantise(rng.uniform(-spread / 2, spread / 2, size=Q))
+    dims = (96, 64)
+    start, got = gpu_run(dims, hmc.HMC_VN4, Q, B, 0.9, 12, 77, vseed=5)
+    want = oracle.sweep(start, hmc.HMC_VN4, dims, B, 0.9, 12, 77, threads=THREADS)
+    assert_same(got, want, f"Q={Q} spread={spread}")
