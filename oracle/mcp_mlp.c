@@ -31,6 +31,12 @@
  *     (C11 - C12 + 3 C44) / 5.
  *   - R = 53-bit fraction of Philox(key = seed, counter = (sample, step, 0,
  *     0x4D435053)) words 0 (high) and 1 (low).
+ *
+ * Pins: the elastic response (closed-form cubic moduli), the yield point
+ * (Schmid law), Eq. (4) and Eq. (2) identities, and the ordering of stored
+ * energy with Schmid factor.  Parity unpinned: the post-yield stress-strain
+ * path and stored energies themselves, which depend on the readings above
+ * and have no published values to check against.
  */
 #include <math.h>
 #include <stdint.h>
