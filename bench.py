@@ -368,8 +368,26 @@ def bench_learned(args, hmc):
         res[name] = ((time.perf_counter() - t0) / args.steps, fb, float(np.max(errs)), tq)
         res[name + "_frac"] = lat.texture_stats(w.grain_bin, w.n_bins)[2]
     drift = float(np.max(np.abs(res["surrogate_frac"] - res["solver_frac"])))
+    # the network's own cost: queries without the audit
+    hmc.hmc_restore(lat.h)
+    q0 = time.perf_counter()
+    for k in range(n_q):
+        hmc.hmc_surrogate_update(lat, M, euler, synth.uniaxial_strain(k + 1, n_q), scale, mode=0, n_audit=0,
+                                 audit_tol=0.25, seed=k)
+    net_ms = (time.perf_counter() - q0) / n_q * 1e3
     lat.close()
     hmc.hmc_mlp_free(M)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the method without the network on the host: the oracle's solver for
+        # one query (every grain under the last strain of the path)
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        tiled = np.tile(synth.uniaxial_strain(n_q, n_q), (w.n_grains, 1))
+        t0 = time.perf_counter()
+        oracle.mcp_solve(euler, tiled, seed=0, threads=threads)
+        cpu = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms per query", "cores": threads, "kind": "oracle",
+               "sample": f"crystal-plasticity solve of the {w.n_grains} grains under the final strain"}
     su = w.n_sites * n_mcs
     _line("Potts site-updates/s with learned stored energy (re-queried every 10 MCS), 1 MI355X",
           su / res["surrogate"][0], args, res["surrogate"][0] * 1e3,
@@ -377,12 +395,13 @@ def bench_learned(args, hmc):
            "mcs_per_step": n_mcs, "queries": n_q},
           solver_in_loop={"value": su / res["solver"][0], "ms_per_step": res["solver"][0] * 1e3,
                           "query_ms": res["solver"][3] / n_q * 1e3},
-          surrogate={"query_ms": res["surrogate"][3] / n_q * 1e3, "fallbacks": res["surrogate"][1],
+          surrogate={"query_ms": res["surrogate"][3] / n_q * 1e3, "query_ms_without_audit": net_ms,
+                     "fallbacks": res["surrogate"][1],
                      "max_audit_rel_err": res["surrogate"][2],
                      "held_out_rel_err_median": float(np.median(rel)),
                      "held_out_rel_err_p95": float(np.percentile(rel, 95)), "train_loss": loss,
                      "train_s": t_train, "solver_data_s": t_gen},
-          texture_fraction_drift_max=drift)
+          texture_fraction_drift_max=drift, cpu_solver_query=cpu)
 
 
 if __name__ == "__main__":

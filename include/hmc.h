@@ -329,10 +329,12 @@ hmc_status hmc_mlp_adam_step(hmc_mlp *M, const float *grad, float lr);
  * macroscopic strain eps6 (6 components, sample frame): B[q] =
  * round-half-even(E_rho[q] * E_scale * 65536), then as hmc_set_grain_energy.
  * euler: host Q x 3 orientations of the grains.  mode 0: the network, with
- * an audit of n_audit grains (drawn with Philox(seed)) against the solver;
- * if the strain leaves the training box (|e_ij| > 2e-3), any prediction is
- * not finite, or the largest relative audit error exceeds audit_tol, every
- * grain is solved instead (*used_solver = 1).  mode 1: the solver for every
+ * an audit of n_audit grains (drawn with Philox(seed)) against the solver,
+ * each solved with its own random stream (the value the fallback would give
+ * it); if the strain leaves the training box (|e_ij| > 2e-3), any prediction
+ * is not finite, or the largest relative audit error exceeds audit_tol,
+ * every grain is solved instead (*used_solver = 1).  The solver keys grain q
+ * by sample index q (hmc_mcp_solve with sample0 = 0).  mode 1: the solver for every
  * grain (the method without the network; M may be NULL).  *audit_err gets
  * the largest relative audit error (0 if no audit ran); B_out (may be NULL)
  * receives the int32[Q] energies set.  Synchronous.

@@ -18,9 +18,10 @@
 // the slip resistance; G = (C11 - C12 + 3 C44) / 5; R is the 53-bit fraction
 // of Philox(key = seed, counter = (sample, step, 0, 0x4D435053)).
 //
-// One thread per crystal.  Symmetric tensors are 6-vectors (xx, yy, zz, yz,
-// xz, xy) with tensor shear components; the slip-system projections P_a,
-// C:P_a and P_a:C:P_a are built on the host and sit in constant memory.
+// Sixteen lanes per crystal (one per slip system).  Symmetric tensors are
+// 6-vectors (xx, yy, zz, yz, xz, xy) with tensor shear components; the
+// slip-system projections P_a, C:P_a and P_a:C:P_a are built on the host and
+// sit in constant memory.
 // Products and sums are not contracted into FMAs, so the arithmetic follows
 // the written expressions.
 #include <hip/hip_runtime.h>
@@ -37,6 +38,7 @@ namespace {
 constexpr double kC11 = 250800.0, kC12 = 150000.0, kC44 = 123500.0;   // MPa (Table 1)
 constexpr double kTau0 = 8.0, kTauS = 122.0, kH0 = 440.0, kBeta = 1000.0;
 constexpr int kMcpThreads = 128;
+constexpr int64_t kGroupBatchMax = 4096;   // up to this many crystals: sixteen lanes per crystal
 
 struct SlipTable {
     double P[12][6];
@@ -101,14 +103,10 @@ __device__ __forceinline__ double voce(double gamma) {
     return kTauS - (kTauS - kTau0) * exp(-kH0 * gamma / (kTauS - kTau0));
 }
 
-__global__ void __launch_bounds__(kMcpThreads)
-mcp_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int64_t n, uint32_t k0, uint32_t k1,
-           uint64_t sample0, double* __restrict__ E_out, double* __restrict__ tauc_out) {
+// Crystal set-up shared by both kernels: the strain rotated into the crystal
+// frame, the number of sub-steps K and the stress increment per sub-step.
+__device__ __forceinline__ void crystal_setup(const double* eu, const double* e6, int& K, Sym& dsig) {
 #pragma clang fp contract(off)
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double* eu = euler + 3 * s;
-    const double* e6 = eps + 6 * s;
     // passive rotation sample -> crystal (Bunge ZXZ)
     const double c1 = cos(eu[0]), s1 = sin(eu[0]), c = cos(eu[1]), sn = sin(eu[1]), c2 = cos(eu[2]), s2 = sin(eu[2]);
     double g[3][3];
@@ -120,18 +118,39 @@ mcp_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int
     for (int i = 0; i < 6; ++i) maxabs = fmax(maxabs, fabs(e6[i]));
     double ec[3][3];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
+        for (int k = 0; k < 3; ++k) {
             double acc = 0.0;
             for (int p = 0; p < 3; ++p)
-                for (int q = 0; q < 3; ++q) acc += g[i][p] * es[p][q] * g[j][q];
-            ec[i][j] = acc;
+                for (int q = 0; q < 3; ++q) acc += g[i][p] * es[p][q] * g[k][q];
+            ec[i][k] = acc;
         }
-    int K = (int)ceil(maxabs / 1e-5);
+    K = (int)ceil(maxabs / 1e-5);
     K = K < 1 ? 1 : (K > 200 ? 200 : K);
     Sym de;
     de.xx = ec[0][0] / K; de.yy = ec[1][1] / K; de.zz = ec[2][2] / K;
     de.yz = ec[1][2] / K; de.xz = ec[0][2] / K; de.xy = ec[0][1] / K;
-    const Sym dsig = stiffness(de);
+    dsig = stiffness(de);
+}
+
+__device__ __forceinline__ double mcp_uniform(uint64_t sample, int step, uint32_t k0, uint32_t k1) {
+    uint32_t o[4];
+    philox4x32_10((uint32_t)sample, (uint32_t)step, 0u, 0x4D435053u, k0, k1, o);
+    return (double)((((uint64_t)o[0] << 32) | o[1]) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// One thread per crystal (large batches: every lane does useful work).
+__global__ void __launch_bounds__(kMcpThreads)
+mcp_thread_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int eps_stride, int64_t n,
+                  uint32_t k0, uint32_t k1, uint64_t sample0, const int32_t* __restrict__ sample_ids,
+                  double* __restrict__ E_out, double* __restrict__ tauc_out) {
+#pragma clang fp contract(off)
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    // the sample index keys the crystal's random stream
+    const uint64_t sample = sample_ids ? (uint64_t)sample_ids[s] : sample0 + (uint64_t)s;
+    int K;
+    Sym dsig;
+    crystal_setup(euler + 3 * s, eps + (int64_t)eps_stride * s, K, dsig);
     Sym sig{0, 0, 0, 0, 0, 0};
     double gamma = 0.0, tc = kTau0;
     for (int step = 1; step <= K; ++step) {
@@ -150,32 +169,30 @@ mcp_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int
             continue;
         }
         const double h = kH0 * exp(-kH0 * gamma / (kTauS - kTau0));
-        // energies of the candidates, then Eq. (1) and Eq. (2) in candidate order
+        // energies of the candidates, then Eq. (1) and Eq. (2) in system order
         double E[12], dg[12];
-        double Emin = 0.0;
-        bool first = true;
+        double Emin = INFINITY;
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
             if (!(cand & (1u << a))) continue;
             dg[a] = (fabs(tau[a]) - tc) / (c_slip.PCP[a] + h);
             const double sgn = tau[a] > 0.0 ? 1.0 : -1.0;
             E[a] = elastic_energy(slipped(str, a, sgn * dg[a]));
-            if (first || E[a] < Emin) Emin = E[a];
-            first = false;
+            Emin = fmin(Emin, E[a]);
         }
-        double Z = 0.0;
+        double w[12], Z = 0.0;
 #pragma unroll
-        for (int a = 0; a < 12; ++a)
-            if (cand & (1u << a)) Z += exp(-kBeta * (E[a] - Emin));
-        uint32_t o[4];
-        philox4x32_10((uint32_t)(sample0 + (uint64_t)s), (uint32_t)step, 0u, 0x4D435053u, k0, k1, o);
-        const double R = (double)((((uint64_t)o[0] << 32) | o[1]) >> 11) * (1.0 / 9007199254740992.0);
+        for (int a = 0; a < 12; ++a) {
+            w[a] = (cand & (1u << a)) ? exp(-kBeta * (E[a] - Emin)) : 0.0;
+            if (cand & (1u << a)) Z += w[a];
+        }
+        const double R = mcp_uniform(sample, step, k0, k1);
         int pick = -1, last = -1;
         double S = 0.0;
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
             if (!(cand & (1u << a))) continue;
-            const double p = exp(-kBeta * (E[a] - Emin)) / Z;
+            const double p = w[a] / Z;
             S += p;
             if (pick < 0 && S - p <= R && R < S) pick = a;
             last = a;
@@ -192,6 +209,83 @@ mcp_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int
     const double G = (kC11 - kC12 + 3.0 * kC44) / 5.0;
     E_out[s] = 2.0 * tc * tc / G;
     if (tauc_out) tauc_out[s] = tc;
+}
+
+// Sixteen lanes per crystal, lane j owning slip system j (j < 12), for small
+// batches where one thread per crystal would leave the chip idle and the
+// serial sub-steps set the time: the resolved shears, candidate returns,
+// energies and Eq. (1) weights of a step are computed side by side; Z and the
+// cumulative intervals of Eq. (2) are then summed in system order by every
+// lane of the group from the gathered weights, so the arithmetic and its
+// order are those of the one-thread kernel and the results are identical.
+constexpr int kGroup = 16;
+
+__global__ void __launch_bounds__(kMcpThreads)
+mcp_group_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int eps_stride, int64_t n,
+                 uint32_t k0, uint32_t k1, uint64_t sample0, const int32_t* __restrict__ sample_ids,
+                 double* __restrict__ E_out, double* __restrict__ tauc_out) {
+#pragma clang fp contract(off)
+    const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+    const int j = (int)(threadIdx.x % kGroup);
+    if (s >= n) return;   // whole groups leave together
+    const int a = j < 12 ? j : 11;   // lanes 12..15 mirror system 11 and never become candidates
+    const uint32_t gbase = (threadIdx.x & 63u) & ~(uint32_t)(kGroup - 1);
+    const uint64_t sample = sample_ids ? (uint64_t)sample_ids[s] : sample0 + (uint64_t)s;
+    int K;
+    Sym dsig;
+    crystal_setup(euler + 3 * s, eps + (int64_t)eps_stride * s, K, dsig);
+    Sym sig{0, 0, 0, 0, 0, 0};
+    double gamma = 0.0, tc = kTau0;
+    for (int step = 1; step <= K; ++step) {
+        Sym str;
+        str.xx = sig.xx + dsig.xx; str.yy = sig.yy + dsig.yy; str.zz = sig.zz + dsig.zz;
+        str.yz = sig.yz + dsig.yz; str.xz = sig.xz + dsig.xz; str.xy = sig.xy + dsig.xy;
+        const double tau = resolved(str, a);
+        const bool is_cand = j < 12 && fabs(tau) > tc;
+        const uint32_t cand = (uint32_t)(__ballot(is_cand) >> gbase) & 0xFFFu;   // bit b: system b
+        if (!cand) {
+            sig = str;
+            continue;
+        }
+        const double h = kH0 * exp(-kH0 * gamma / (kTauS - kTau0));
+        double dg = 0.0, E = INFINITY;
+        if (is_cand) {
+            dg = (fabs(tau) - tc) / (c_slip.PCP[a] + h);
+            const double sgn = tau > 0.0 ? 1.0 : -1.0;
+            E = elastic_energy(slipped(str, a, sgn * dg));
+        }
+        double Emin = E;   // the minimum does not depend on the order
+        for (int off = kGroup / 2; off >= 1; off >>= 1) Emin = fmin(Emin, __shfl_xor(Emin, off, kGroup));
+        const double w = is_cand ? exp(-kBeta * (E - Emin)) : 0.0;
+        double wall[12];
+#pragma unroll
+        for (int b = 0; b < 12; ++b) wall[b] = __shfl(w, b, kGroup);
+        double Z = 0.0;
+#pragma unroll
+        for (int b = 0; b < 12; ++b)
+            if (cand & (1u << b)) Z += wall[b];
+        const double R = mcp_uniform(sample, step, k0, k1);
+        int pick = -1, last = -1;
+        double S = 0.0;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) {
+            if (!(cand & (1u << b))) continue;
+            const double p = wall[b] / Z;
+            S += p;
+            if (pick < 0 && S - p <= R && R < S) pick = b;
+            last = b;
+        }
+        if (pick < 0) pick = last;
+        const double dgp = __shfl(dg, pick, kGroup), taup = __shfl(tau, pick, kGroup);
+        sig = slipped(str, pick, (taup > 0.0 ? 1.0 : -1.0) * dgp);
+        gamma += dgp;
+        tc = voce(gamma);
+    }
+    if (j == 0) {
+        const double G = (kC11 - kC12 + 3.0 * kC44) / 5.0;
+        E_out[s] = 2.0 * tc * tc / G;
+        if (tauc_out) tauc_out[s] = tc;
+    }
 }
 
 SlipTable build_slip_table() {
@@ -232,7 +326,8 @@ SlipTable build_slip_table() {
 }  // namespace
 
 hmc_status mcp_solve_device(const double* d_euler, const double* d_eps, int64_t n, uint64_t seed, uint64_t sample0,
-                            double* d_E, double* d_tauc, hipStream_t stream) {
+                            double* d_E, double* d_tauc, hipStream_t stream, int eps_stride,
+                            const int32_t* d_sample_ids) {
     static bool uploaded = false;
     if (!uploaded) {
         const SlipTable t = build_slip_table();
@@ -240,9 +335,16 @@ hmc_status mcp_solve_device(const double* d_euler, const double* d_eps, int64_t 
         uploaded = true;
     }
     if (n == 0) return HMC_OK;
-    const uint64_t blocks = ((uint64_t)n + kMcpThreads - 1) / kMcpThreads;
-    mcp_kernel<<<dim3((unsigned)blocks), kMcpThreads, 0, stream>>>(d_euler, d_eps, n, (uint32_t)(seed & 0xFFFFFFFFu),
-                                                                  (uint32_t)(seed >> 32), sample0, d_E, d_tauc);
+    const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
+    if (n <= kGroupBatchMax) {
+        const uint64_t blocks = ((uint64_t)n * kGroup + kMcpThreads - 1) / kMcpThreads;
+        mcp_group_kernel<<<dim3((unsigned)blocks), kMcpThreads, 0, stream>>>(d_euler, d_eps, eps_stride, n, k0, k1,
+                                                                             sample0, d_sample_ids, d_E, d_tauc);
+    } else {
+        const uint64_t blocks = ((uint64_t)n + kMcpThreads - 1) / kMcpThreads;
+        mcp_thread_kernel<<<dim3((unsigned)blocks), kMcpThreads, 0, stream>>>(d_euler, d_eps, eps_stride, n, k0, k1,
+                                                                              sample0, d_sample_ids, d_E, d_tauc);
+    }
     HMC_HIP(hipGetLastError());
     return HMC_OK;
 }
@@ -258,7 +360,7 @@ extern "C" hmc_status hmc_mcp_solve(const double* euler, const double* eps, int6
     if (n >= (1ll << 31)) return fail(HMC_E_INVAL, "n must be below 2^31");
     if (n == 0) return HMC_OK;
     if (on_device) {
-        HMC_TRY(mcp_solve_device(euler, eps, n, seed, sample0, E_out, tauc_out, nullptr));
+        HMC_TRY(mcp_solve_device(euler, eps, n, seed, sample0, E_out, tauc_out, nullptr, 6, nullptr));
         HMC_HIP(hipStreamSynchronize(nullptr));
         return HMC_OK;
     }
@@ -274,7 +376,8 @@ extern "C" hmc_status hmc_mcp_solve(const double* euler, const double* eps, int6
     if (st == HMC_OK) e = hipMemcpy(de, euler, be, hipMemcpyHostToDevice);
     if (st == HMC_OK && e == hipSuccess) e = hipMemcpy(dp, eps, bp, hipMemcpyHostToDevice);
     if (st == HMC_OK && e == hipSuccess)
-        st = mcp_solve_device((const double*)de, (const double*)dp, n, seed, sample0, (double*)dE, (double*)dT, nullptr);
+        st = mcp_solve_device((const double*)de, (const double*)dp, n, seed, sample0, (double*)dE, (double*)dT, nullptr,
+                              6, nullptr);
     if (st == HMC_OK && e == hipSuccess) e = hipMemcpy(E_out, dE, bE, hipMemcpyDeviceToHost);
     if (st == HMC_OK && e == hipSuccess && tauc_out) e = hipMemcpy(tauc_out, dT, bE, hipMemcpyDeviceToHost);
     dev_free(de, be);

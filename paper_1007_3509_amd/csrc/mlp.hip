@@ -33,7 +33,8 @@
 
 namespace hmc {
 hmc_status mcp_solve_device(const double* d_euler, const double* d_eps, int64_t n, uint64_t seed, uint64_t sample0,
-                            double* d_E, double* d_tauc, hipStream_t stream);
+                            double* d_E, double* d_tauc, hipStream_t stream, int eps_stride,
+                            const int32_t* d_sample_ids);
 }
 
 namespace {
@@ -51,15 +52,15 @@ constexpr double kPi = 3.14159265358979323846;
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void features_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int64_t n,
-                                float* __restrict__ X) {
+__global__ void features_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int eps_stride,
+                                int64_t n, float* __restrict__ X) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     float* x = X + kIn * s;
     x[0] = (float)(euler[3 * s + 0] / kPi - 1.0);
     x[1] = (float)(2.0 * euler[3 * s + 1] / kPi - 1.0);
     x[2] = (float)(euler[3 * s + 2] / kPi - 1.0);
-    for (int k = 0; k < 6; ++k) x[3 + k] = (float)(eps[6 * s + k] / kStrainBox);
+    for (int k = 0; k < 6; ++k) x[3 + k] = (float)(eps[(int64_t)eps_stride * s + k] / kStrainBox);
 }
 
 __global__ void targets_kernel(const double* __restrict__ E, int64_t n, double mean, double inv_std,
@@ -307,7 +308,7 @@ hmc_status make_features(hmc_mlp* M, const double* euler, const double* eps, int
     HMC_TRY(upload_or_alias(eps, (size_t)n * 6 * 8, on_device, M->eps, &dp, M->stream, "mlp strain"));
     HMC_TRY(M->X.ensure((size_t)n * kIn * 4, "mlp features"));
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    features_kernel<<<blocks, 256, 0, M->stream>>>(de, dp, n, M->X.as<float>());
+    features_kernel<<<blocks, 256, 0, M->stream>>>(de, dp, 6, n, M->X.as<float>());
     HMC_HIP(hipGetLastError());
     return HMC_OK;
 }
@@ -601,60 +602,69 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     hmc_mlp scratch_holder;   // buffers when no network is given
     if (!W) W = &scratch_holder;
     if (!W->stream) W->stream = L->stream;
-    // every grain under the same strain
-    std::vector<double> eps((size_t)Q * 6);
+    // every grain under the same strain: one 6-vector read with stride 0
     bool in_box = true;
     for (int k = 0; k < 6; ++k) {
         if (!std::isfinite(eps6[k])) return fail(HMC_E_INVAL, "non-finite strain");
         if (std::fabs(eps6[k]) > kStrainBox * (1.0 + 1e-12)) in_box = false;
     }
-    for (int32_t q = 0; q < Q; ++q) std::memcpy(&eps[(size_t)q * 6], eps6, 48);
+    const int32_t na = std::max(0, std::min(n_audit, Q));
     hmc_status st = W->euler.ensure((size_t)Q * 24, "grain orientations");
-    if (st == HMC_OK) st = W->eps.ensure((size_t)Q * 48, "grain strains");
+    if (st == HMC_OK) st = W->eps.ensure(48, "grain strain");
     if (st == HMC_OK) st = W->E.ensure((size_t)Q * 8, "grain energies");
     if (st == HMC_OK) st = W->Bq.ensure((size_t)Q * 4, "quantised energies");
+    if (st == HMC_OK && na > 0) st = W->audit_idx.ensure((size_t)na * 4, "audit grains");
+    if (st == HMC_OK && na > 0) st = W->Eaudit.ensure((size_t)na * 32, "audit orientations and energies");
     hipError_t e = hipSuccess;
     if (st == HMC_OK) e = hipMemcpyAsync(W->euler.p, euler, (size_t)Q * 24, hipMemcpyHostToDevice, W->stream);
-    if (st == HMC_OK && e == hipSuccess)
-        e = hipMemcpyAsync(W->eps.p, eps.data(), (size_t)Q * 48, hipMemcpyHostToDevice, W->stream);
+    if (st == HMC_OK && e == hipSuccess) e = hipMemcpyAsync(W->eps.p, eps6, 48, hipMemcpyHostToDevice, W->stream);
     bool solver = mode == 1 || !in_box;
     double err = 0.0;
     if (st == HMC_OK && e == hipSuccess && !solver) {
-        st = make_features(W, W->euler.as<double>(), W->eps.as<double>(), Q, 1);
-        if (st == HMC_OK) {
+        HMC_TRY(W->X.ensure((size_t)Q * kIn * 4, "mlp features"));
+        features_kernel<<<(unsigned)((Q + 255) / 256), 256, 0, W->stream>>>(W->euler.as<double>(),
+                                                                            W->eps.as<double>(), 0, Q,
+                                                                            W->X.as<float>());
+        e = hipGetLastError();
+        if (e == hipSuccess) {
             predict_kernel<<<(unsigned)((Q + kPredThreads - 1) / kPredThreads), kPredThreads, 0, W->stream>>>(
                 W->theta.as<float>(), W->X.as<float>(), Q, W->mean, W->sdev, W->E.as<double>(), nullptr);
             e = hipGetLastError();
         }
-        // audit: n_audit grains drawn with Philox, solved exactly
-        const int32_t na = std::min(n_audit, Q);
+        // audit: n_audit grains drawn with Philox, solved exactly with their
+        // own random streams, i.e. the values the fallback would give them
+        std::vector<int32_t> ids((size_t)na);
+        std::vector<double> predicted((size_t)Q), Es((size_t)na);
         if (st == HMC_OK && e == hipSuccess && na > 0) {
-            std::vector<double> ae((size_t)na * 3), ap((size_t)na * 6), Ep((size_t)na), Es((size_t)na);
-            std::vector<int32_t> ids((size_t)na);
+            std::vector<double> ae((size_t)na * 3);
             for (int32_t a = 0; a < na; ++a) {
                 ids[a] = (int32_t)(((uint64_t)philox_u32(seed, (uint32_t)a, 1u, 0x41554449u) * (uint64_t)Q) >> 32);
                 std::memcpy(&ae[(size_t)a * 3], euler + (size_t)ids[a] * 3, 24);
-                std::memcpy(&ap[(size_t)a * 6], eps6, 48);
             }
-            std::vector<double> predicted((size_t)Q);
+            double* d_ae = W->Eaudit.as<double>();
+            e = hipMemcpyAsync(W->audit_idx.p, ids.data(), (size_t)na * 4, hipMemcpyHostToDevice, W->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(d_ae, ae.data(), (size_t)na * 24, hipMemcpyHostToDevice, W->stream);
+            if (e == hipSuccess)
+                st = mcp_solve_device(d_ae, W->eps.as<double>(), na, seed, 0, d_ae + (size_t)na * 3, nullptr,
+                                      W->stream, 0, W->audit_idx.as<int32_t>());
+            if (st == HMC_OK && e == hipSuccess)
+                e = hipMemcpyAsync(Es.data(), d_ae + (size_t)na * 3, (size_t)na * 8, hipMemcpyDeviceToHost,
+                                   W->stream);
+        }
+        if (st == HMC_OK && e == hipSuccess)
             e = hipMemcpyAsync(predicted.data(), W->E.p, (size_t)Q * 8, hipMemcpyDeviceToHost, W->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(W->stream);
-            if (e == hipSuccess) st = hmc_mcp_solve(ae.data(), ap.data(), na, seed, 0, 0, Es.data(), nullptr);
-            if (st == HMC_OK && e == hipSuccess) {
-                for (int32_t a = 0; a < na; ++a) {
-                    const double p = predicted[(size_t)ids[a]];
-                    if (!std::isfinite(p)) { err = INFINITY; break; }
-                    err = std::max(err, std::fabs(p - Es[(size_t)a]) / std::fabs(Es[(size_t)a]));
-                }
-                for (int32_t q = 0; q < Q && std::isfinite(err); ++q)
-                    if (!std::isfinite(predicted[(size_t)q])) err = INFINITY;
-                if (!(err <= audit_tol)) solver = true;
-            }
+        if (st == HMC_OK && e == hipSuccess) e = hipStreamSynchronize(W->stream);
+        if (st == HMC_OK && e == hipSuccess) {
+            for (int32_t q = 0; q < Q; ++q)
+                if (!std::isfinite(predicted[(size_t)q])) err = INFINITY;
+            for (int32_t a = 0; a < na && std::isfinite(err); ++a)
+                err = std::max(err, std::fabs(predicted[(size_t)ids[a]] - Es[(size_t)a]) / std::fabs(Es[(size_t)a]));
+            if (!(err <= audit_tol)) solver = true;
         }
     }
     if (st == HMC_OK && e == hipSuccess && solver) {
         st = mcp_solve_device(W->euler.as<double>(), W->eps.as<double>(), Q, seed, 0, W->E.as<double>(), nullptr,
-                              W->stream);
+                              W->stream, 0, nullptr);
     }
     if (st == HMC_OK && e == hipSuccess) {
         quantise_kernel<<<(Q + 255) / 256, 256, 0, W->stream>>>(W->E.as<double>(), Q, E_scale * 65536.0,
@@ -666,7 +676,7 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
         e = hipMemcpyAsync(B.data(), W->Bq.p, (size_t)Q * 4, hipMemcpyDeviceToHost, W->stream);
     if (st == HMC_OK && e == hipSuccess) e = hipStreamSynchronize(W->stream);
     if (W == &scratch_holder) {
-        for (DevBuf* b : {&W->X, &W->euler, &W->eps, &W->E, &W->Bq}) b->release();
+        for (DevBuf* b : {&W->X, &W->euler, &W->eps, &W->E, &W->Bq, &W->audit_idx, &W->Eaudit}) b->release();
     }
     if (st != HMC_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "surrogate update");

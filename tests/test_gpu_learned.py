@@ -153,6 +153,10 @@ def test_surrogate_driver_audit_and_fallback():
         B_inf, used, err = hmc.hmc_surrogate_update(lat, M, euler, strain, 0.15 / 0.002, mode=0, n_audit=4,
                                                     audit_tol=1e9)
         assert used and not np.isfinite(err) and np.array_equal(B_inf, B_solver)
+        # ... also without an audit
+        B_inf0, used, err = hmc.hmc_surrogate_update(lat, M, euler, strain, 0.15 / 0.002, mode=0, n_audit=0,
+                                                     audit_tol=1e9)
+        assert used and not np.isfinite(err) and np.array_equal(B_inf0, B_solver)
     finally:
         hmc.hmc_mlp_free(M)
         lat.close()
@@ -177,3 +181,43 @@ def test_surrogate_driven_sweep_bit_exact_with_oracle():
     finally:
         hmc.hmc_mlp_free(M)
         lat.close()
+
+
+def test_audit_compares_with_the_fallback_values():
+    # the audited grains are solved with their own random streams, so the
+    # audit error is the network's error against exactly what the fallback
+    # would set for those grains
+    G, seed = 500, 31
+    euler, _ = synth.crystal_inputs(G, 13)
+    lat = hmc.Lattice((32, 32, 32), hmc.HMC_VN6, G, voronoi_seed=6)
+    M = hmc.hmc_mlp_create(4)
+    try:
+        th, _ = hmc.hmc_mlp_get_params(M)
+        hmc.hmc_mlp_set_params(M, 0.1 * th, [0.0017, 0.0003])
+        strain = synth.uniaxial_strain(40)
+        _, used, err = hmc.hmc_surrogate_update(lat, M, euler, strain, 0.15 / 0.002, mode=0, n_audit=48,
+                                                audit_tol=1e9, seed=seed)
+        assert not used
+        tiled = np.tile(strain, (G, 1))
+        Es = hmc.hmc_mcp_solve(euler, tiled, seed=seed)          # grain q keyed by sample q
+        pred = hmc.hmc_mlp_predict(M, euler, tiled)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        r0 = oracle.philox4x32_10([[a, 1, 0, 0x41554449] for a in range(48)], key)[:, 0].astype(np.uint64)
+        ids = ((r0 * np.uint64(G)) >> np.uint64(32)).astype(np.int64)
+        want = np.max(np.abs(pred[ids] - Es[ids]) / Es[ids])
+        assert err == pytest.approx(want, rel=1e-12)
+    finally:
+        hmc.hmc_mlp_free(M)
+        lat.close()
+
+
+def test_mcp_batch_kernels_agree_exactly():
+    # batches up to 4096 crystals run sixteen lanes per crystal, larger ones
+    # one thread per crystal; both sum Eq. (1)-(2) in system order
+    euler, eps = _inputs(5000, 91)
+    say("[gpu] mcp group vs thread kernels")
+    E_big = hmc.hmc_mcp_solve(euler, eps, seed=8)
+    E_small = hmc.hmc_mcp_solve(euler[:4000], eps[:4000], seed=8)
+    E_tail = hmc.hmc_mcp_solve(euler[4000:], eps[4000:], seed=8, sample0=4000)
+    assert np.array_equal(E_big[:4000], E_small)
+    assert np.array_equal(E_big[4000:], E_tail)
