@@ -25,42 +25,79 @@ namespace hmc {
 namespace {
 
 constexpr int kVorThreads = 256;
-constexpr int kVorChunk = 1024;
 
-template <typename Dist, typename Spin>
+// Nearest seed point of every site by expanding rings of a uniform cell grid.
+// The grid has nc_k cells along axis k; a coordinate X (fixed point, 256 per
+// site) lies in cell floor(X nc_k / (256 L_k)), so every cell is at least
+// w_k = floor(256 L_k / nc_k) wide.  After the rings 0..r around the site's
+// cell are searched, any point not yet seen lies at least r cells away along
+// some axis, hence at periodic distance >= r w_min; the search stops once the
+// best squared distance is below (r w_min)^2, which also settles ties (an
+// unseen point cannot be as close).  Ties between seen points go to the lower
+// index, as in a scan in index order.
+template <typename Dist, typename Spin, int D>
 __global__ void __launch_bounds__(kVorThreads)
-voronoi_kernel(Spin* __restrict__ out, const int32_t* __restrict__ pts, int32_t G, uint32_t Lx, uint32_t Ly,
-               uint32_t Lz, int ndim, uint64_t N) {
-    __shared__ int32_t sp[kVorChunk * 3];
+voronoi_kernel(Spin* __restrict__ out, const int4* __restrict__ pts, const int32_t* __restrict__ cell_start, int ncx,
+               int ncy, int ncz, uint32_t wmin, uint32_t Lx, uint32_t Ly, uint32_t Lz, uint64_t N) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < N;
-    const int32_t x = (int32_t)(i % Lx), y = (int32_t)((i / Lx) % Ly), z = (int32_t)(i / ((uint64_t)Lx * Ly));
-    const int32_t pos[3] = {256 * x, 256 * y, 256 * z};
-    const int32_t span[3] = {(int32_t)(256 * Lx), (int32_t)(256 * Ly), (int32_t)(256 * Lz)};
+    if (i >= N) return;
+    const uint32_t x = (uint32_t)(i % Lx), y = (uint32_t)((i / Lx) % Ly), z = (uint32_t)(i / ((uint64_t)Lx * Ly));
+    const int32_t px = (int32_t)(256u * x), py = (int32_t)(256u * y), pz = (int32_t)(256u * z);
+    const int32_t spx = (int32_t)(256u * Lx), spy = (int32_t)(256u * Ly), spz = (int32_t)(256u * Lz);
+    const int cx = (int)((uint64_t)x * (uint64_t)ncx / Lx), cy = (int)((uint64_t)y * (uint64_t)ncy / Ly);
+    const int cz = D == 3 ? (int)((uint64_t)z * (uint64_t)ncz / Lz) : 0;
     Dist best = ~(Dist)0;
-    int32_t bg = 0;
-    for (int32_t g0 = 0; g0 < G; g0 += kVorChunk) {
-        const int32_t n = min(kVorChunk, G - g0);
-        __syncthreads();
-        for (int32_t k = threadIdx.x; k < n * 3; k += blockDim.x) sp[k] = pts[(size_t)g0 * 3 + k];
-        __syncthreads();
-        if (active) {
-            for (int32_t g = 0; g < n; ++g) {
-                Dist d2 = 0;
-                for (int a = 0; a < ndim; ++a) {
-                    int32_t dd = sp[3 * g + a] - pos[a];
-                    dd = dd < 0 ? -dd : dd;
-                    dd = min(dd, span[a] - dd);
-                    d2 += (Dist)dd * (Dist)dd;
-                }
-                if (d2 < best) {   // ascending g: ties keep the lower index
-                    best = d2;
-                    bg = g0 + g;
+    int32_t bg = 0x7FFFFFFF;
+    auto scan_cell = [&](int ax, int ay, int az) __attribute__((always_inline)) {
+        const int cell = ax + ncx * (ay + ncy * az);
+        const int p1 = cell_start[cell + 1];
+        for (int p = cell_start[cell]; p < p1; ++p) {
+            const int4 q = pts[p];
+            int32_t dx = q.x - px;
+            dx = dx < 0 ? -dx : dx;
+            dx = min(dx, spx - dx);
+            int32_t dy = q.y - py;
+            dy = dy < 0 ? -dy : dy;
+            dy = min(dy, spy - dy);
+            Dist d2 = (Dist)dx * (Dist)dx + (Dist)dy * (Dist)dy;
+            if (D == 3) {
+                int32_t dz = q.z - pz;
+                dz = dz < 0 ? -dz : dz;
+                dz = min(dz, spz - dz);
+                d2 += (Dist)dz * (Dist)dz;
+            }
+            if (d2 < best || (d2 == best && q.w < bg)) {
+                best = d2;
+                bg = q.w;
+            }
+        }
+    };
+    auto wrap = [](int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+    for (int r = 0;; ++r) {
+        // offsets along each axis, each cyclic cell at most once
+        const int lox = -min(r, (ncx - 1) / 2), hix = min(r, ncx / 2);
+        const int loy = -min(r, (ncy - 1) / 2), hiy = min(r, ncy / 2);
+        const int loz = D == 3 ? -min(r, (ncz - 1) / 2) : 0, hiz = D == 3 ? min(r, ncz / 2) : 0;
+        bool any = false;
+        for (int dz = loz; dz <= hiz; ++dz) {
+            const int az = wrap(cz + dz, ncz);
+            for (int dy = loy; dy <= hiy; ++dy) {
+                const int ay = wrap(cy + dy, ncy);
+                const bool shell_yz = max(abs(dy), abs(dz)) == r;
+                if (shell_yz) {
+                    for (int dx = lox; dx <= hix; ++dx) scan_cell(wrap(cx + dx, ncx), ay, az);
+                    any = true;
+                } else {   // only the two x ends of this row belong to ring r
+                    if (lox == -r) { scan_cell(wrap(cx - r, ncx), ay, az); any = true; }
+                    if (hix == r && r > 0) { scan_cell(wrap(cx + r, ncx), ay, az); any = true; }
                 }
             }
         }
+        if (!any) break;   // every cell has been searched
+        const uint64_t reach = (uint64_t)r * wmin;
+        if ((uint64_t)best < reach * reach) break;
     }
-    if (active) out[i] = (Spin)bg;
+    out[i] = (Spin)bg;
 }
 
 constexpr int kHistThreads = 256;
@@ -166,42 +203,88 @@ int grid_for(uint64_t n, int threads, int cap) {
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed) {
     const int32_t G = L->Q;
     const int ndim = L->ndim;
+    const uint32_t Lx = (uint32_t)L->desc.dims[0], Ly = (uint32_t)L->desc.dims[1];
+    const uint32_t Lz = ndim == 3 ? (uint32_t)L->desc.dims[2] : 1u;
+    const uint32_t Ls[3] = {Lx, Ly, Lz};
+    const uint64_t N = (uint64_t)L->N;
+    // seed points (fixed point, 256 per site) from Philox
     std::vector<int32_t> pts((size_t)G * 3, 0);
     const uint32_t k0 = (uint32_t)(vseed & 0xFFFFFFFFu), k1 = (uint32_t)(vseed >> 32);
     for (int32_t g = 0; g < G; ++g) {
         uint32_t r[4];
         philox4x32_10((uint32_t)g, 0u, 0u, 0x564F524Eu, k0, k1, r);
         for (int a = 0; a < ndim; ++a)
-            pts[(size_t)g * 3 + a] = (int32_t)(((uint64_t)r[a] * ((uint64_t)L->desc.dims[a] * 256u)) >> 32);
+            pts[(size_t)g * 3 + a] = (int32_t)(((uint64_t)r[a] * ((uint64_t)Ls[a] * 256u)) >> 32);
     }
-    void* dpts = nullptr;
-    const size_t bytes = pts.size() * sizeof(int32_t);
-    HMC_TRY(dev_alloc(&dpts, bytes, "voronoi points"));
-    hipError_t e = hipMemcpyAsync(dpts, pts.data(), bytes, hipMemcpyHostToDevice, L->stream);
-    const uint32_t Lx = (uint32_t)L->desc.dims[0], Ly = (uint32_t)L->desc.dims[1];
-    const uint32_t Lz = ndim == 3 ? (uint32_t)L->desc.dims[2] : 1u;
+    // cell grid with about two points per cell
+    int nc[3] = {1, 1, 1};
+    const double per_axis = std::pow((double)G / (2.0 * (double)N), 1.0 / ndim);
+    uint32_t wmin = 0xFFFFFFFFu;
+    for (int a = 0; a < ndim; ++a) {
+        nc[a] = (int)std::max(1.0, std::min((double)Ls[a], std::floor(Ls[a] * per_axis)));
+        wmin = std::min(wmin, (uint32_t)((256ull * Ls[a]) / (uint64_t)nc[a]));
+    }
+    const size_t ncells = (size_t)nc[0] * nc[1] * nc[2];
+    std::vector<int32_t> cell_of((size_t)G), start(ncells + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        size_t c = 0, mul = 1;
+        for (int a = 0; a < ndim; ++a) {
+            const uint64_t ca = (uint64_t)pts[(size_t)g * 3 + a] * (uint64_t)nc[a] / (256ull * Ls[a]);
+            c += (size_t)ca * mul;
+            mul *= (size_t)nc[a];
+        }
+        cell_of[g] = (int32_t)c;
+        ++start[c + 1];
+    }
+    for (size_t c = 0; c < ncells; ++c) start[c + 1] += start[c];
+    std::vector<int4> sorted((size_t)G);
+    {
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int32_t g = 0; g < G; ++g) {
+            const size_t at = (size_t)fill[cell_of[g]]++;
+            sorted[at] = make_int4(pts[(size_t)g * 3], pts[(size_t)g * 3 + 1], pts[(size_t)g * 3 + 2], g);
+        }
+    }
+    void *dpts = nullptr, *dstart = nullptr;
+    const size_t bp = sorted.size() * sizeof(int4), bs = start.size() * sizeof(int32_t);
+    HMC_TRY(dev_alloc(&dpts, bp, "voronoi points"));
+    hmc_status st = dev_alloc(&dstart, bs, "voronoi cells");
+    if (st != HMC_OK) {
+        dev_free(dpts, bp);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(dpts, sorted.data(), bp, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dstart, start.data(), bs, hipMemcpyHostToDevice, L->stream);
     // 32-bit distances suffice while ndim * (128 * L_max)^2 < 2^32
-    uint64_t half = 128ull * std::max(Lx, std::max(Ly, Lz));
+    const uint64_t half = 128ull * std::max(Lx, std::max(Ly, Lz));
     const bool d32 = (uint64_t)ndim * half * half < (1ull << 32);
-    const uint64_t N = (uint64_t)L->N;
     const dim3 grid((unsigned)((N + kVorThreads - 1) / kVorThreads));
+    const int4* P = static_cast<const int4*>(dpts);
+    const int32_t* S = static_cast<const int32_t*>(dstart);
     if (e == hipSuccess) {
         void* out = L->spins[L->cur];
+#define HMC_VORONOI(DIST, SPIN, DIM)                                                                               \
+    voronoi_kernel<DIST, SPIN, DIM><<<grid, kVorThreads, 0, L->stream>>>((SPIN*)out, P, S, nc[0], nc[1], nc[2], wmin, \
+                                                                         Lx, Ly, Lz, N)
         if (L->desc.spin == HMC_I16) {
-            if (d32) voronoi_kernel<uint32_t, int16_t><<<grid, kVorThreads, 0, L->stream>>>(
-                         (int16_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
-            else voronoi_kernel<uint64_t, int16_t><<<grid, kVorThreads, 0, L->stream>>>(
-                     (int16_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+            if (ndim == 2) {
+                if (d32) HMC_VORONOI(uint32_t, int16_t, 2); else HMC_VORONOI(uint64_t, int16_t, 2);
+            } else {
+                if (d32) HMC_VORONOI(uint32_t, int16_t, 3); else HMC_VORONOI(uint64_t, int16_t, 3);
+            }
         } else {
-            if (d32) voronoi_kernel<uint32_t, int32_t><<<grid, kVorThreads, 0, L->stream>>>(
-                         (int32_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
-            else voronoi_kernel<uint64_t, int32_t><<<grid, kVorThreads, 0, L->stream>>>(
-                     (int32_t*)out, (const int32_t*)dpts, G, Lx, Ly, Lz, ndim, N);
+            if (ndim == 2) {
+                if (d32) HMC_VORONOI(uint32_t, int32_t, 2); else HMC_VORONOI(uint64_t, int32_t, 2);
+            } else {
+                if (d32) HMC_VORONOI(uint32_t, int32_t, 3); else HMC_VORONOI(uint64_t, int32_t, 3);
+            }
         }
+#undef HMC_VORONOI
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    dev_free(dpts, bytes);
+    dev_free(dpts, bp);
+    dev_free(dstart, bs);
     if (e != hipSuccess) return hip_fail(e, "voronoi");
     return HMC_OK;
 }
