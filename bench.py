@@ -43,6 +43,7 @@ WORKLOADS = {
     "schmid_2d_1024": synth.schmid_2d_1024,
     "schmid_3d_256": synth.schmid_3d_256,
     "stress_2d_16384": synth.stress_2d_16384,
+    "stress_3d_512": synth.stress_3d_512,
 }
 SPECIAL = ("ensemble_moore8", "learned_3d_256")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}

@@ -170,12 +170,13 @@ def schmid_2d_1024():
     return schmid_2d(name="schmid_2d_1024")
 
 
-def schmid_3d(side=256, G=20000, seed=3003, n_mcs=500, vseed=3, sseed=3, kT=0.6, name=None):
+def schmid_3d(side=256, G=20000, seed=3003, n_mcs=500, vseed=3, sseed=3, kT=0.6, name=None, spin=None):
     rng = np.random.Generator(np.random.PCG64(seed))
     g = quat_to_matrix(shoemake_quaternions(rng, G))   # passive: crystal = g . sample
     load = g @ np.array([0.0, 0.0, 1.0])        # [001] load axis in the crystal frame
     m = schmid_factor(load)
-    return Workload(name or f"schmid_3d_{side}", (side, side, side), VN6, I16, G, kT, n_mcs, vseed,
+    return Workload(name or f"schmid_3d_{side}", (side, side, side), VN6, spin if spin is not None else I16, G, kT,
+                    n_mcs, vseed,
                     sseed, quantise(0.15 * m), m=m, euler=matrix_to_bunge(g))
 
 
@@ -187,6 +188,12 @@ def stress_2d_16384():
     """16384^2 VN4 int16 (512 MiB per buffer, beyond the 256 MiB Infinity
     Cache), 32000 grains with energies as schmid_2d_1024, kT 0.5, 100 MCS."""
     return schmid_2d(side=16384, G=32000, seed=2003, n_mcs=100, vseed=7, sseed=7, name="stress_2d_16384")
+
+
+def stress_3d_512():
+    """512^3 VN6 int32 (512 MiB per buffer), 160000 grains (mean volume as
+    schmid_3d_256) with energies as schmid_3d_256, kT 0.6, 50 MCS."""
+    return schmid_3d(side=512, G=160000, seed=3005, n_mcs=50, vseed=9, sseed=9, name="stress_3d_512", spin=I32)
 
 
 def ensemble_moore8(count=64, seed=4004, n_mcs=1000):
