@@ -158,6 +158,67 @@ def voronoi(dims, G, vseed, method="grid", threads=1):
     return out.reshape(tuple(reversed(dims)))
 
 
+def sweep_pair(spins, nbr, dims, Jp, B, kT, n_mcs, seed, mcs0=0, proposal=PROP_NEIGHBOUR, threads=1):
+    """As sweep with a bond energy per pair of spins (Eq. (7)'s J_{q_i,q_n}):
+    Jp int32[Q, Q], symmetric, zero diagonal, 2^-16 units."""
+    src = np.asarray(spins)
+    s = np.ascontiguousarray(src.astype(np.int32).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
+    jp = np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
+    Q = len(b)
+    assert jp.shape == (Q, Q)
+    d = _dims3(dims)
+    f = lib().orc_sweep_pair
+    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.c_uint64, C.c_int32, C.c_uint64, C.c_int]
+    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), _ptr(jp, C.c_int32),
+           _ptr(b, C.c_int32), int(Q), float(kT), int(mcs0), int(n_mcs), int(seed), int(threads))
+    if rc != 0:
+        raise ValueError(f"orc_sweep_pair failed with {rc}")
+    return s.reshape(src.shape).astype(src.dtype)
+
+
+def delta_energy_pair(spins, nbr, dims, Jp, B, i, q_new):
+    s = np.ascontiguousarray(np.asarray(spins, dtype=np.int32).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
+    jp = np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
+    d = _dims3(dims)
+    f = lib().orc_delta_energy_pair
+    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                  C.POINTER(C.c_int32), C.c_int64, C.c_int32]
+    f.restype = C.c_int64
+    return int(f(_ptr(s, C.c_int32), int(nbr), _ptr(d, C.c_int32), _ptr(jp, C.c_int32), len(b),
+                 _ptr(b, C.c_int32), int(i), int(q_new)))
+
+
+def misorientation_deg(e1, e2):
+    """Cubic misorientation angle (degrees) of two Bunge orientations."""
+    f = lib().orc_misorientation_deg
+    f.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    f.restype = C.c_double
+    a = np.ascontiguousarray(np.asarray(e1, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(e2, dtype=np.float64))
+    return float(f(_ptr(a, C.c_double), _ptr(b, C.c_double)))
+
+
+def read_shockley(theta_deg, J_max, theta_m_deg):
+    f = lib().orc_read_shockley
+    f.argtypes = [C.c_double, C.c_double, C.c_double]
+    f.restype = C.c_double
+    return float(f(float(theta_deg), float(J_max), float(theta_m_deg)))
+
+
+def pair_table(euler, J_max, theta_m_deg):
+    """Q x Q Read-Shockley bond energies (2^-16 units) of Q orientations."""
+    e = np.ascontiguousarray(np.asarray(euler, dtype=np.float64).reshape(-1, 3))
+    Q = e.shape[0]
+    out = np.empty((Q, Q), dtype=np.int32)
+    f = lib().orc_pair_table
+    f.argtypes = [C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+    f(_ptr(e, C.c_double), Q, float(J_max), float(theta_m_deg), _ptr(out, C.c_int32))
+    return out
+
+
 def boundary_sites(spins, nbr, dims, Q):
     """Sites with a spin in [0, Q) and at least one unlike neighbour: the
     only sites whose trial can change the state (Sec. 3)."""

@@ -224,6 +224,29 @@ int64_t orc_delta_energy(const int32_t *spins, int nbr, const int32_t dims_in[3]
     return (int64_t)J_fx * (unlike_after - unlike_before) + (int64_t)B[q_new] - (int64_t)B[q];
 }
 
+/* The same change when every bond carries its own energy (the paper's
+ * J_{q_i,q_n} of Eq. (7)): with Jp[a*Q + b] the energy of an unlike bond
+ * between spins a and b (symmetric, zero diagonal, 2^-16 units),
+ *   dE = sum over the M neighbours s_k of (Jp[q_new][s_k] - Jp[q][s_k])
+ *        + B[q_new] - B[q];
+ * a like bond costs nothing, which the zero diagonal expresses. */
+int64_t orc_delta_energy_pair(const int32_t *spins, int nbr, const int32_t dims_in[3],
+                              const int32_t *Jp, int32_t Q, const int32_t *B, int64_t i, int32_t q_new)
+{
+    int off[26][3];
+    int64_t dims[3] = {dims_in[0], dims_in[1], dims_in[2]};
+    int M = orc_offsets(nbr, off), k;
+    int64_t x = i % dims[0], y = (i / dims[0]) % dims[1], z = i / (dims[0] * dims[1]);
+    int32_t q = spins[i];
+    int64_t after = 0, before = 0;
+    for (k = 0; k < M; ++k) {
+        int32_t s = spins[orc_neighbour_index(dims, off, k, x, y, z)];
+        after += Jp[(int64_t)q_new * Q + s];
+        before += Jp[(int64_t)q * Q + s];
+    }
+    return after - before + (int64_t)B[q_new] - (int64_t)B[q];
+}
+
 /* ----------------------------------------------------------------- sweep */
 
 /* n_mcs Monte Carlo steps of red/black Metropolis on a periodic lattice.
@@ -237,9 +260,9 @@ int64_t orc_delta_energy(const int32_t *spins, int nbr, const int32_t dims_in[3]
  *           trial reads the state as it was when the half step began).
  *
  * Returns 0, or -1 on bad arguments, -2 if an energy change leaves int32. */
-int orc_sweep(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
-              int32_t J_fx, const int32_t *B, int32_t Q, float kT,
-              uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
+static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
+                      int32_t J_fx, const int32_t *Jp, const int32_t *B, int32_t Q, float kT,
+                      uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
 {
     int off[26][3];
     int M = orc_offsets(nbr, off);
@@ -284,7 +307,8 @@ int orc_sweep(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
                     q_new = (int32_t)(((int64_t)q + 1 + (int64_t)s) % Q);
                 }
                 if (q_new == q) continue;
-                d = orc_delta_energy(before, nbr, dims_in, J_fx, B, i, q_new);
+                d = Jp ? orc_delta_energy_pair(before, nbr, dims_in, Jp, Q, B, i, q_new)
+                       : orc_delta_energy(before, nbr, dims_in, J_fx, B, i, q_new);
                 if (d > INT32_MAX || d < INT32_MIN) { overflow = 1; continue; }
                 if (d <= 0 || r[1] < orc_threshold(d, kT)) spins[i] = q_new;
             }
@@ -292,6 +316,23 @@ int orc_sweep(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
     }
     free(before);
     return overflow ? -2 : 0;
+}
+
+int orc_sweep(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
+              int32_t J_fx, const int32_t *B, int32_t Q, float kT,
+              uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
+{
+    return sweep_impl(spins, nbr, proposal, dims_in, J_fx, NULL, B, Q, kT, mcs0, n_mcs, seed, threads);
+}
+
+/* As orc_sweep with a bond energy per pair of spins: Jp int32[Q*Q],
+ * symmetric, zero diagonal, 2^-16 units. */
+int orc_sweep_pair(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
+                   const int32_t *Jp, const int32_t *B, int32_t Q, float kT,
+                   uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
+{
+    if (!Jp) return -1;
+    return sweep_impl(spins, nbr, proposal, dims_in, 0, Jp, B, Q, kT, mcs0, n_mcs, seed, threads);
 }
 
 /* -------------------------------------------------------------- Voronoi */
