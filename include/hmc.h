@@ -132,6 +132,35 @@ hmc_status hmc_lattice_free(hmc_lattice *L);
  * Errors: INVAL; RANGE if |J_fx|*M + 2 max|B| >= 2^31. */
 hmc_status hmc_set_grain_energy(hmc_lattice *L, const int32_t *B_fx, int32_t n_grains, int32_t on_device);
 
+/* Bond energy per pair of spin values (Eq. (7) writes J for each pair
+ * q_i, q_n; the closing section names misorientation-dependent boundary
+ * energy as the use of that freedom).  Jp: int32[Q*Q], row-major, Jp[a*Q+b]
+ * the energy of an unlike bond between spins a and b in 2^-16 units;
+ * symmetric, zero diagonal, entries in [0, 2^24]; host (on_device = 0) or
+ * device memory (on_device = 1); copied (4 Q^2 bytes on the device).
+ * While set, hmc_sweep uses dE = sum over the M neighbours s_k of
+ * (Jp[q'][s_k] - Jp[q][s_k]) + B[q'] - B[q] with the same trials, the same
+ * random numbers and the threshold T(d) of every d > 0; the descriptor's
+ * J_fx is not used.  Jp = NULL restores the uniform bond energy J_fx.
+ * Ensembles do not take lattices in this mode.  Synchronous.
+ * Errors: INVAL (NULL lattice, n_grains != Q, table not symmetric, nonzero
+ * diagonal, entries out of range), RANGE (M max Jp + 2 max|B| >= 2^31),
+ * NOMEM, DEVICE. */
+hmc_status hmc_set_pair_energy(hmc_lattice *L, const int32_t *Jp, int32_t n_grains, int32_t on_device);
+
+/* Read-Shockley pair energies of Q grain orientations, computed on the GPU:
+ * theta = misorientation angle of grains a and b (smallest rotation angle of
+ * g_b g_a^T over the 24 proper rotations of the cube; euler: Q x 3 Bunge
+ * angles, passive sample -> crystal), J = J_max (theta/theta_m)
+ * (1 - ln(theta/theta_m)) below theta_m (degrees) and J_max above, written
+ * as round-half-even(J * 65536) into Jp_out int32[Q*Q] (symmetric, zero
+ * diagonal).  The paper gives no law for J; Read and Shockley, Phys. Rev. 78
+ * (1950) 275.  euler and Jp_out are both host (on_device = 0) or both device
+ * arrays.  Synchronous.  Errors: INVAL (NULL, Q outside [1, 46340], J_max
+ * outside [0, 256], theta_m <= 0), NOMEM, DEVICE. */
+hmc_status hmc_misorientation_energy(const double *euler, int32_t Q, double J_max, double theta_m_deg,
+                                     int32_t on_device, int32_t *Jp_out);
+
 /* n_mcs Monte Carlo steps of red/black Metropolis (Sec. 4) at temperature
  * kT (the paper's effective temperature alpha_mc with J = 1), drawing from
  * the Philox stream of `seed`.  Steps are numbered from the lattice's MC

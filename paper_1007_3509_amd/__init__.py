@@ -54,6 +54,9 @@ _SIGS = [
                                      C.POINTER(C.c_void_p)]),
     ("hmc_lattice_free", C.c_int32, [C.c_void_p]),
     ("hmc_set_grain_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_set_pair_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_misorientation_energy", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                              C.c_void_p]),
     ("hmc_sweep", C.c_int32, [C.c_void_p, C.c_float, C.c_int32, C.c_uint64]),
     ("hmc_texture_stats", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double), C.c_void_p]),
@@ -176,6 +179,22 @@ def hmc_lattice_free(h):
 def hmc_set_grain_energy(h, B_fx):
     b = np.ascontiguousarray(np.asarray(B_fx, dtype=np.int32))
     _check(lib().hmc_set_grain_energy(h, _ptr(b), int(b.size), 0))
+
+
+def hmc_set_pair_energy(h, Jp):
+    """Pair bond energies int32[Q, Q] (2^-16 units), or None for the uniform J_fx."""
+    if Jp is None:
+        _check(lib().hmc_set_pair_energy(h, None, 0, 0))
+        return
+    j = np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
+    _check(lib().hmc_set_pair_energy(h, _ptr(j), j.shape[0], 0))
+
+
+def hmc_misorientation_energy(euler, J_max, theta_m_deg):
+    e = np.ascontiguousarray(np.asarray(euler, dtype=np.float64).reshape(-1, 3))
+    out = np.empty((e.shape[0], e.shape[0]), dtype=np.int32)
+    _check(lib().hmc_misorientation_energy(_ptr(e), e.shape[0], float(J_max), float(theta_m_deg), 0, _ptr(out)))
+    return out
 
 
 def hmc_sweep(h, kT, n_mcs, seed):
@@ -443,6 +462,9 @@ class Lattice:
 
     def set_grain_energy(self, B_fx):
         hmc_set_grain_energy(self.h, B_fx)
+
+    def set_pair_energy(self, Jp):
+        hmc_set_pair_energy(self.h, Jp)
 
     def sweep(self, kT, n_mcs, seed):
         hmc_sweep(self.h, kT, n_mcs, seed)

@@ -132,6 +132,8 @@ struct Table {
 uint32_t threshold_value(int64_t d, float kT);
 hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax,
                        hipStream_t stream);
+// Threshold table T(d) for every d in [0, Dmax] (pair bond energies).
+hmc_status build_pair_table(hmc_lattice* L, float kT);
 void free_table(Table& tab);
 
 // ---------------------------------------------------------------- tiling
@@ -183,6 +185,15 @@ struct hmc_lattice_s {
     int64_t prof_launches = 0, prof_su = 0;
     unsigned long long* d_trials = nullptr;   // kTrialSlots counters of Philox draws while profiling
     unsigned long long* d_count = nullptr;    // boundary-site count
+
+    // bond energy per pair of spins (Eq. (7)'s J_{q_i,q_n}); off: uniform J_fx
+    bool pair = false;
+    int32_t* d_Jp = nullptr;                  // int32[Q*Q]
+    int32_t Jp_max = 0;
+    uint32_t* d_Tg = nullptr;                 // T(d), d = 0..Tg_Dmax
+    size_t Tg_bytes = 0;
+    uint32_t Tg_kT_bits = 0;
+    int32_t Tg_Dmax = -1;
 };
 
 namespace hmc {

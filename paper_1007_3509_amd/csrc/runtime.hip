@@ -152,6 +152,32 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     return HMC_OK;
 }
 
+hmc_status build_pair_table(hmc_lattice* L, float kT) {
+    uint32_t bits;
+    std::memcpy(&bits, &kT, sizeof bits);
+    // largest possible d: every bond of the new spin at the largest energy,
+    // none of the old, plus the spread of the grain energies
+    const int64_t Dmax = (int64_t)L->M * L->Jp_max + ((int64_t)L->Bmax - L->Bmin);
+    if (L->d_Tg && L->Tg_kT_bits == bits && L->Tg_Dmax == Dmax) return HMC_OK;
+    const size_t bytes = (size_t)(Dmax + 1) * sizeof(uint32_t);
+    if (bytes > kTableCapBytes) return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
+    std::vector<uint32_t> host((size_t)Dmax + 1);
+    host[0] = 0xFFFFFFFFu;   // d <= 0 is accepted before the table is read
+    for (int64_t d = 1; d <= Dmax; ++d) host[(size_t)d] = threshold_value(d, kT);
+    if (L->Tg_bytes != bytes) {
+        dev_free(L->d_Tg, L->Tg_bytes);
+        L->d_Tg = nullptr;
+        L->Tg_bytes = 0;
+        HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_Tg), bytes, "threshold table"));
+        L->Tg_bytes = bytes;
+    }
+    HMC_HIP(hipMemcpyAsync(L->d_Tg, host.data(), bytes, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    L->Tg_kT_bits = bits;
+    L->Tg_Dmax = (int32_t)Dmax;
+    return HMC_OK;
+}
+
 void free_table(Table& tab) {
     dev_free(tab.dev, tab.bytes);
     tab = Table{};
@@ -182,12 +208,14 @@ hmc_status validate_desc(const hmc_lattice_desc* d, int32_t n_grains) {
     return HMC_OK;
 }
 
-hmc_status check_energy_range(const hmc_lattice* L, int32_t Bmin, int32_t Bmax) {
+hmc_status check_energy_range(const hmc_lattice* L, int32_t Bmin, int32_t Bmax, int32_t Jbond) {
     const int64_t maxabs = std::max<int64_t>(std::llabs((int64_t)Bmin), std::llabs((int64_t)Bmax));
-    if ((int64_t)L->desc.J_fx * L->M + 2 * maxabs >= (1ll << 31))
-        return fail(HMC_E_RANGE, "J_fx*M + 2 max|B| must stay below 2^31");
+    if ((int64_t)Jbond * L->M + 2 * maxabs >= (1ll << 31))
+        return fail(HMC_E_RANGE, "(largest bond energy)*M + 2 max|B| must stay below 2^31");
     return HMC_OK;
 }
+
+int32_t bond_max(const hmc_lattice* L) { return L->pair ? L->Jp_max : L->desc.J_fx; }
 
 void destroy(hmc_lattice* L) {
     if (!L) return;
@@ -202,6 +230,8 @@ void destroy(hmc_lattice* L) {
     dev_free(L->d_gbin, (size_t)L->Q * 4);
     dev_free(L->d_trials, kTrialSlots * sizeof(unsigned long long));
     dev_free(L->d_count, sizeof(unsigned long long));
+    dev_free(L->d_Jp, (size_t)L->Q * (size_t)L->Q * 4);
+    dev_free(L->d_Tg, L->Tg_bytes);
     free_table(L->table);
     for (auto& e : L->events) {
         (void)hipEventDestroy(e.first);
@@ -366,12 +396,52 @@ hmc_status hmc_set_grain_energy(hmc_lattice* L, const int32_t* B_fx, int32_t n_g
         lo = std::min(lo, v);
         hi = std::max(hi, v);
     }
-    HMC_TRY(check_energy_range(L, lo, hi));
+    HMC_TRY(check_energy_range(L, lo, hi, bond_max(L)));
     HMC_HIP(hipMemcpyAsync(L->dB, h.data(), (size_t)n_grains * 4, hipMemcpyHostToDevice, L->stream));
     HMC_HIP(hipStreamSynchronize(L->stream));
     L->hB.swap(h);
     L->Bmin = lo;
     L->Bmax = hi;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_pair_energy(hmc_lattice* L, const int32_t* Jp, int32_t n_grains, int32_t on_device) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    const size_t QQ = (size_t)L->Q * (size_t)L->Q;
+    if (!Jp) {   // back to the uniform J_fx
+        dev_free(L->d_Jp, QQ * 4);
+        L->d_Jp = nullptr;
+        L->pair = false;
+        L->Jp_max = 0;
+        return HMC_OK;
+    }
+    if (n_grains != L->Q) return fail(HMC_E_INVAL, "n_grains must equal the lattice's Q");
+    if (QQ * 4 > ((size_t)1 << 33)) return fail(HMC_E_INVAL, "pair table larger than 8 GiB");
+    std::vector<int32_t> h(QQ);
+    if (on_device) {
+        HMC_HIP(hipMemcpyAsync(h.data(), Jp, QQ * 4, hipMemcpyDeviceToHost, L->stream));
+        HMC_HIP(hipStreamSynchronize(L->stream));
+    } else {
+        std::memcpy(h.data(), Jp, QQ * 4);
+    }
+    int32_t jmax = 0;
+    const size_t Q = (size_t)L->Q;
+    for (size_t a = 0; a < Q; ++a) {
+        if (h[a * Q + a] != 0) return fail(HMC_E_INVAL, "pair table diagonal must be zero");
+        for (size_t b = a + 1; b < Q; ++b) {
+            const int32_t v = h[a * Q + b];
+            if (v != h[b * Q + a]) return fail(HMC_E_INVAL, "pair table must be symmetric");
+            if (v < 0 || v > (1 << 24)) return fail(HMC_E_INVAL, "pair energies must lie in [0, 2^24]");
+            jmax = std::max(jmax, v);
+        }
+    }
+    HMC_TRY(check_energy_range(L, L->Bmin, L->Bmax, jmax));
+    if (!L->d_Jp) HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_Jp), QQ * 4, "pair energies"));
+    HMC_HIP(hipMemcpyAsync(L->d_Jp, h.data(), QQ * 4, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    L->pair = true;
+    L->Jp_max = jmax;
     return HMC_OK;
 }
 
@@ -600,6 +670,7 @@ hmc_status hmc_ensemble_create(hmc_lattice* const* lats, int32_t n, hmc_ensemble
             return fail(HMC_E_INVAL, "ensemble members must share neighbourhood, spin type and trial mode");
         for (int32_t j = 0; j < i; ++j)
             if (lats[j] == lats[i]) return fail(HMC_E_INVAL, "lattice " + std::to_string(i) + " appears twice");
+        if (lats[i]->pair) return fail(HMC_E_INVAL, "ensembles take lattices with the uniform bond energy only");
     }
     hmc_ensemble* E = new hmc_ensemble();
     E->lats.assign(lats, lats + n);

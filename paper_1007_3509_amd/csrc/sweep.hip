@@ -75,6 +75,9 @@ struct LatArgs {
     uint32_t bw, m_bw;        // bucket width and its reciprocal (m_bw = 0: divide)
     uint32_t uniform;         // 1: symmetric trial spins
     unsigned long long* trials;   // when not null: kTrialSlots counters of Philox draws (queued trials)
+    const int32_t* Jp;        // pair bond energies int32[Q*Q] (pair mode)
+    const uint32_t* Tg;       // pair mode: T(d) for d = 0..Dmax
+    int32_t Dmax;
 };
 
 // Per-launch arguments: the LDS box and its precomputed reciprocals.
@@ -151,7 +154,7 @@ __device__ __forceinline__ int nbr_offset(uint32_t k, int BX, int BXY) {
 // One tile: stage tile + halo, run g.P colour passes in LDS, write the interior.
 // Ends with every thread past its last LDS access of the tile (callers that
 // process another tile put a barrier before reusing LDS).
-template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair = false>
 __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g, uint32_t tx, uint32_t ty,
                                              uint32_t tz, unsigned char* smem) {
     using Tr = Traits<NBR>;
@@ -292,6 +295,18 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                 if (qn >= a.Q) qn -= a.Q;
             }
             if (qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
+            if constexpr (kPair) {
+                // dE = sum_k (Jp[q'][s_k] - Jp[q][s_k]) + B[q'] - B[q]; a
+                // neighbour value outside [0, Q) bonds with nothing
+                const int32_t* Jq = a.Jp + (size_t)q * (uint32_t)a.Q;
+                const int32_t* Jn = a.Jp + (size_t)qn * (uint32_t)a.Q;
+                int32_t d = Bq[qn] - bq;
+#pragma unroll
+                for (int k = 0; k < M; ++k)
+                    if ((uint32_t)nb[k] < (uint32_t)a.Q) d += Jn[nb[k]] - Jq[nb[k]];
+                if (d <= 0 || r.r1 < a.Tg[min(d, a.Dmax)]) box[idx] = (Spin)qn;
+                return;
+            }
             int cq = 0, cn = 0;
 #pragma unroll
             for (int k = 0; k < M; ++k) {
@@ -466,7 +481,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 }
 
 // One lattice: one workgroup per tile.
-template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair>
 __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs g, uint32_t xcd_group) {
     extern __shared__ __align__(16) unsigned char smem[];
     // Consecutive workgroups are spread over the 8 XCDs round-robin; regroup
@@ -477,7 +492,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs
     const uint32_t tx = b % a.ntx;
     const uint32_t ty = (b / a.ntx) % a.nty;
     const uint32_t tz = b / (a.ntx * a.nty);
-    process_tile<NBR, Spin, kGrainsInLds, kSwar>(a, g, tx, ty, tz, smem);
+    process_tile<NBR, Spin, kGrainsInLds, kSwar, kPair>(a, g, tx, ty, tz, smem);
 }
 
 // Ensemble: persistent workgroups walk the ragged tile table of all lattices.
@@ -505,19 +520,23 @@ ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restr
 }
 
 template <int NBR, bool kSwar>
-const void* kernel_for(int spin, bool grains_in_lds, bool ensemble) {
+const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair) {
     if (ensemble) {
+        if (pair) return nullptr;
         if (spin == HMC_I16)
             return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, true, kSwar>)
                                  : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, false, kSwar>);
         return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true, false>)
                              : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false, false>);
     }
+    if (pair)   // bond energies from the pair table; grain energies read from global memory
+        return spin == HMC_I16 ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, true>)
+                               : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, true>);
     if (spin == HMC_I16)
-        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true, kSwar>)
-                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar>);
-    return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true, false>)
-                         : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false>);
+        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true, kSwar, false>)
+                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, false>);
+    return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true, false, false>)
+                         : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, false>);
 }
 
 // The 64-bit phase-1 path needs 16-bit spins, a checkerboard and rows of a
@@ -526,16 +545,16 @@ bool use_swar(int nbr, int spin, uint32_t BX) {
     return spin == HMC_I16 && (nbr == HMC_VN4 || nbr == HMC_VN6) && BX % 4 == 0;
 }
 
-const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar) {
+const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar, bool pair = false) {
     switch (nbr) {
     case HMC_VN4:
-        return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble)
-                    : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble);
+        return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble, pair)
+                    : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble, pair);
+    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble, pair);
     case HMC_VN6:
-        return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble)
-                    : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble);
-    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble);
+        return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble, pair)
+                    : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble, pair);
+    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble, pair);
     }
 }
 
@@ -757,13 +776,23 @@ hmc_status settle_borrowed(hmc_lattice* L) {
 
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
     if (n_mcs == 0) return HMC_OK;
-    HMC_TRY(build_table(L->table, kT, L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
-    if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
+    if (L->pair) {
+        HMC_TRY(build_pair_table(L, kT));
+    } else {
+        HMC_TRY(build_table(L->table, kT, L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
+        if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
+    }
     Tiling t = L->tiling;
     HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
     L->tiling = t;
 
     LatArgs a = lat_args(L, t, seed);
+    if (L->pair) {   // the per-row bounds are not used
+        a.Jp = L->d_Jp;
+        a.Tg = L->d_Tg;
+        a.Dmax = L->Tg_Dmax;
+        a.nbound = 0;
+    }
     const uint32_t ntiles = a.ntx * a.nty * (a.Lz / a.TZ);
     const uint32_t xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
 
@@ -783,7 +812,7 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
-        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar);
+        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair);
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
         a.t0 = (uint32_t)t_next;
@@ -872,6 +901,8 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
 
 hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* seed, int32_t n_mcs) {
     if (n_mcs == 0) return HMC_OK;
+    for (const hmc_lattice* L : E->lats)
+        if (L->pair) return fail(HMC_E_STATE, "an ensemble member was given pair bond energies");
     if (!E->prepared) HMC_TRY(ensemble_prepare(E));
     hmc_lattice* L0 = E->lats[0];
     const int C = L0->C;
