@@ -44,6 +44,7 @@ WORKLOADS = {
     "schmid_3d_256": synth.schmid_3d_256,
     "stress_2d_16384": synth.stress_2d_16384,
     "stress_3d_512": synth.stress_3d_512,
+    "misorientation_2d_1024": synth.misorientation_2d_1024,
 }
 SPECIAL = ("ensemble_moore8", "learned_3d_256")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}
@@ -89,22 +90,36 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
+    pair = w.extra.get("pair")
+    extra = {}
+    if pair:
+        # the oracle's own table; the GPU run of the check takes the same table
+        Jp = oracle.pair_table(w.euler, *pair)
+        extra["pair_table_max_abs_diff_gpu_vs_oracle"] = int(np.max(np.abs(gpu_check.table().astype(np.int64) - Jp)))
+
+        def run(n, th):
+            return oracle.sweep_pair(start, w.nbr, w.dims, Jp, w.B, w.kT, n, w.sweep_seed, threads=th)
+    else:
+        Jp = None
+
+        def run(n, th):
+            return oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, n, w.sweep_seed, threads=th)
     probe = 2
     t0 = time.perf_counter()
-    oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, probe, w.sweep_seed, threads=threads)
+    run(probe, threads)
     per_mcs = (time.perf_counter() - t0) / probe
     sample = int(max(1, min(n_mcs, budget_s / max(per_mcs, 1e-9))))
     t0 = time.perf_counter()
-    out = oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, sample, w.sweep_seed, threads=threads)
+    out = run(sample, threads)
     dt = time.perf_counter() - t0
-    exact = bool(np.array_equal(gpu_check(sample), out))
+    exact = bool(np.array_equal(gpu_check(sample, Jp), out))
     # single-thread reference semantics on a quarter of the budget
     t0 = time.perf_counter()
-    oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, 1, w.sweep_seed, threads=1)
+    run(1, 1)
     per1 = time.perf_counter() - t0
     sample1 = int(max(1, min(n_mcs, budget_s / 4 / max(per1, 1e-9))))
     t0 = time.perf_counter()
-    out1 = oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, sample1, w.sweep_seed, threads=1)
+    out1 = run(sample1, 1)
     dt1 = time.perf_counter() - t0
     same_1t = bool(np.array_equal(out1, out)) if sample1 == sample else None
     return {
@@ -117,6 +132,7 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
         "gpu_bit_exact_on_sample": exact,
         "single_core": {"value": w.n_sites * sample1 / dt1, "sample_mcs": sample1,
                         "same_as_threaded": same_1t},
+        **extra,
     }
 
 
@@ -139,6 +155,11 @@ def main():
     n_mcs = args.mcs or w.n_mcs
     lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
     lat.set_grain_energy(w.B)
+    pair = w.extra.get("pair")
+    gpu_table = None
+    if pair:   # bond energy per pair of grains, built on the GPU from the orientations
+        gpu_table = hmc.hmc_misorientation_energy(w.euler, *pair)
+        lat.set_pair_energy(gpu_table)
     if args.tiling:
         lat.set_tiling(*[int(v) for v in args.tiling.split(",")])
     start = lat.spins()
@@ -242,10 +263,13 @@ def main():
         "final_mean_area": stats[1],
     }
     if not args.no_cpu_baseline:
-        def gpu_check(sample):
+        def gpu_check(sample, Jp=None):  # noqa: E306
+            if Jp is not None:
+                lat.set_pair_energy(Jp)
             hmc.hmc_restore(lat.h)
             lat.sweep(w.kT, sample, w.sweep_seed)
             return lat.spins().astype(np.int32)
+        gpu_check.table = lambda: gpu_table
         out["cpu_baseline"] = cpu_baseline(w, start.astype(np.int32), n_mcs, args.cpu_seconds, gpu_check)
     lat.close()
     print(json.dumps(out), flush=True)

@@ -190,6 +190,16 @@ def stress_2d_16384():
     return schmid_2d(side=16384, G=32000, seed=2003, n_mcs=100, vseed=7, sseed=7, name="stress_2d_16384")
 
 
+def misorientation_2d_1024():
+    """schmid_2d_1024 with a bond energy per pair of grains: Read-Shockley
+    (J_max 1, theta_m 15 deg) of Shoemake-uniform orientations (PCG64 2004)."""
+    w = schmid_2d(name="misorientation_2d_1024")
+    rng = np.random.Generator(np.random.PCG64(2004))
+    w.euler = matrix_to_bunge(quat_to_matrix(shoemake_quaternions(rng, w.n_grains)))
+    w.extra["pair"] = (1.0, 15.0)
+    return w
+
+
 def stress_3d_512():
     """512^3 VN6 int32 (512 MiB per buffer), 160000 grains (mean volume as
     schmid_3d_256) with energies as schmid_3d_256, kT 0.6, 50 MCS."""
