@@ -45,6 +45,7 @@ WORKLOADS = {
     "stress_2d_16384": synth.stress_2d_16384,
     "stress_3d_512": synth.stress_3d_512,
     "misorientation_2d_1024": synth.misorientation_2d_1024,
+    "moore26_3d_128": synth.moore26_3d_128,
 }
 SPECIAL = ("ensemble_moore8", "learned_3d_256")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}
@@ -230,7 +231,8 @@ def main():
             "grains": w.n_grains,
             "kT": w.kT,
             "mcs_per_step": n_mcs,
-            "tiling": {"tile": list(tiling[:3]), "mcs_per_launch": tiling[3]},
+            "tiling": ({"tile": list(tiling[:3]), "mcs_per_launch": tiling[3]} if tiling[3] > 0
+                       else {"tile": list(tiling[:3]), "colour_passes_per_launch": -tiling[3]}),
         },
         "roofline": {
             "bound": "hbm",

@@ -196,12 +196,15 @@ hmc_status hmc_restore(hmc_lattice *L);
 hmc_status hmc_get_mcs(const hmc_lattice *L, uint64_t *mcs);
 hmc_status hmc_set_mcs(hmc_lattice *L, uint64_t mcs);
 
-/* Tiling of the sweep kernel: interior tile (tx, ty, tz) and MC steps fused
- * per launch.  Zero means "choose automatically".  Each tile side must be an
- * even divisor of the lattice side; the LDS box (tile + halo of
- * mcs_per_launch * C sites per side) must fit the kernel's LDS budget.
- * Results do not depend on the tiling.  get_tiling returns the tiling in
- * force as int32[4]. */
+/* Tiling of the sweep kernel: interior tile (tx, ty, tz) and the work fused
+ * per launch: mcs_per_launch > 0 MC steps, or mcs_per_launch < 0 for
+ * -mcs_per_launch colour passes (launches that cover part of an MC step,
+ * useful with 4 or 8 colours).  Zero means "choose automatically".  Each
+ * tile side must be an even divisor of the lattice side; the LDS box (tile +
+ * a halo of one site per fused colour pass) must fit the kernel's LDS
+ * budget; at most 64 passes per launch.  Results do not depend on the
+ * tiling.  get_tiling returns the tiling in force as int32[4] with the same
+ * sign convention. */
 hmc_status hmc_set_tiling(hmc_lattice *L, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch);
 hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
 

@@ -139,8 +139,11 @@ void free_table(Table& tab);
 // ---------------------------------------------------------------- tiling
 
 struct Tiling {
-    int32_t tx = 0, ty = 0, tz = 0, k = 0;   // interior tile, MC steps per launch (0: automatic)
+    // interior tile; k > 0: MC steps per launch, k < 0: -k colour passes per
+    // launch (part of an MC step), 0: automatic
+    int32_t tx = 0, ty = 0, tz = 0, k = 0;
 };
+inline int launch_passes(const Tiling& t, int C) { return t.k > 0 ? t.k * C : -t.k; }
 
 // --------------------------------------------------------------- lattice
 

@@ -560,12 +560,12 @@ hmc_status hmc_set_mcs(hmc_lattice* L, uint64_t mcs) {
 hmc_status hmc_set_tiling(hmc_lattice* L, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch) {
     g_error.clear();
     if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
-    if (tx < 0 || ty < 0 || tz < 0 || mcs_per_launch < 0) return fail(HMC_E_INVAL, "tiling values must be >= 0");
+    if (tx < 0 || ty < 0 || tz < 0) return fail(HMC_E_INVAL, "tile sides must be >= 0");
     Tiling t;
     t.tx = tx;
     t.ty = ty;
     t.tz = L->ndim == 3 ? tz : 1;
-    t.k = mcs_per_launch;
+    t.k = mcs_per_launch;   // < 0: -mcs_per_launch colour passes per launch
     HMC_TRY(choose_tiling(L, t, true));
     L->tiling = t;
     L->tiling_explicit = true;

@@ -67,6 +67,7 @@ struct LatArgs {
     uint32_t TX, TY, TZ;
     uint32_t ntx, nty;
     uint32_t t0;              // MC step index of the first pass
+    uint32_t c0;              // colour of the first pass (launches may start inside an MC step)
     uint32_t k0, k1;          // Philox key
     int32_t J_fx;
     int32_t Q;
@@ -253,8 +254,9 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 
     unsigned long long drawn = 0;   // queued trials of this tile (thread 0; profiling only)
     for (uint32_t pass = 0; pass < g.P; ++pass) {
-        const uint32_t c = pass % C;
-        const uint32_t t = a.t0 + pass / C;
+        const uint32_t gp = a.c0 + pass;   // pass counted from colour 0 of MC step t0
+        const uint32_t c = gp % C;
+        const uint32_t t = a.t0 + gp / C;
         const uint32_t lo = pass + 1;
         const uint32_t lox = lo + (HX - H);   // the same ring counted from the padded x edge
         const uint32_t loz = (D == 3) ? lo : 0;
@@ -695,9 +697,9 @@ hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t max
             return fail(HMC_E_INVAL, "tile side " + std::to_string(sides[ax]) +
                                          " must be an even divisor of the lattice side " + std::to_string(dims[ax]));
     }
-    if (r.k < 1 || r.k * C > kMaxPasses)
-        return fail(HMC_E_INVAL, "mcs_per_launch * colours must be in [1, " + std::to_string(kMaxPasses) + "]");
-    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, r.k * C, false);
+    if (r.k == 0 || launch_passes(r, C) > kMaxPasses)
+        return fail(HMC_E_INVAL, "colour passes per launch must be in [1, " + std::to_string(kMaxPasses) + "]");
+    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, launch_passes(r, C), false);
     if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
         return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
     if ((int64_t)lay.bytes > lds_limit_bytes())
@@ -719,7 +721,8 @@ std::vector<Tiling> default_tilings(int nbr) {
     case HMC_VN4: return {T(64, 64, 1, 4), T(32, 32, 1, 4), T(16, 16, 1, 2)};
     case HMC_MOORE8: return {T(64, 64, 1, 2), T(32, 32, 1, 2), T(16, 16, 1, 1)};
     case HMC_VN6: return {T(64, 16, 16, 1), T(32, 32, 16, 1), T(32, 16, 16, 1), T(16, 16, 16, 1), T(8, 8, 8, 1)};
-    default: return {T(8, 8, 8, 1), T(4, 4, 4, 1)};
+    // eight colours: four colour passes per launch keep the halo at four rings
+    default: return {T(32, 16, 16, -4), T(16, 16, 16, -4), T(8, 8, 8, -2), T(4, 4, 4, -1)};
     }
 }
 
@@ -754,7 +757,8 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
                 if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], d.tz);
                 if (L->ndim == 2) r.tz = 1;
                 if (r.k == 0) r.k = d.k;
-                const Layout lay = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, r.k * L->C, false);
+                const Layout lay =
+                    box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, launch_passes(r, L->C), false);
                 if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
             }
         }
@@ -796,26 +800,28 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     const uint32_t ntiles = a.ntx * a.nty * (a.Lz / a.TZ);
     const uint32_t xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
 
-    // MC steps per launch.  A borrowed spin buffer must hold the result: when
-    // the launch count would leave it in the second buffer, the last launch
-    // is split in two (results do not depend on the split).
+    // Colour passes per launch.  A borrowed spin buffer must hold the result:
+    // when the launch count would leave it in the second buffer, the last
+    // launch is split in two (results do not depend on the split).
+    const int P = launch_passes(t, L->C);
     std::vector<int> chunks;
-    for (int32_t rem = n_mcs; rem > 0; rem -= std::min<int32_t>(t.k, rem)) chunks.push_back(std::min<int32_t>(t.k, rem));
+    for (int64_t rem = (int64_t)n_mcs * L->C; rem > 0; rem -= std::min<int64_t>(P, rem))
+        chunks.push_back((int)std::min<int64_t>(P, rem));
     if (L->borrowed && ((L->cur + (int)chunks.size()) & 1) && !chunks.empty() && chunks.back() >= 2) {
-        const int kl = chunks.back();
-        chunks.back() = kl / 2;
-        chunks.push_back(kl - kl / 2);
+        const int pl = chunks.back();
+        chunks.back() = pl / 2;
+        chunks.push_back(pl - pl / 2);
     }
-    uint64_t t_next = L->mcs;
-    for (const int k : chunks) {
-        const int passes = k * L->C;
+    int64_t gp0 = 0;   // passes done in this call
+    for (const int passes : chunks) {
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
         const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair);
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
-        a.t0 = (uint32_t)t_next;
+        a.t0 = (uint32_t)(L->mcs + (uint64_t)(gp0 / L->C));
+        a.c0 = (uint32_t)(gp0 % L->C);
         uint32_t xg = xcd_group;
         void* args[] = {&a, &g, &xg};
         if (L->profiling) {
@@ -831,12 +837,12 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
             HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream, ev.first,
                                        ev.second, 0));
             L->prof_launches += 1;
-            L->prof_su += (int64_t)k * L->N;
+            L->prof_su += (int64_t)passes * L->N / L->C;
         } else {
             HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream));
         }
         L->cur ^= 1;
-        t_next += (uint64_t)k;
+        gp0 += passes;
     }
     L->mcs += (uint64_t)n_mcs;
     return settle_borrowed(L);
@@ -859,7 +865,7 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
             t.tx = largest_even_divisor_at_most(g[0], d.tx);
             t.ty = largest_even_divisor_at_most(g[1], d.ty);
             t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], d.tz) : 1;
-            t.k = d.k;
+            t.k = d.k > 0 ? d.k : 1;   // ensemble launches cover whole MC steps
             const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, t, t.k * L0->C, false);
             if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
         }

@@ -38,13 +38,16 @@ std::vector<Tiling> candidates(const hmc_lattice_desc& d) {
     const int C = nbr_info(d.nbr).C;
     const std::vector<int> sides2 = {16, 32, 64, 128, 256};
     const std::vector<int> sides3 = {4, 8, 16, 32, 64};
-    const std::vector<int> ks = {1, 2, 4, 8};
+    // MC steps per launch; with four or eight colours also launches of 1, 2
+    // or 4 colour passes (negative k), whose halos are thinner
+    std::vector<int> ks = {1, 2, 4, 8};
+    if (C >= 4) ks.insert(ks.end(), {-1, -2, -4});
     auto divides = [&](int s, int L) { return s <= L && L % s == 0; };
     if (d.ndim == 2) {
         for (int tx : sides2)
             for (int ty : sides2)
                 for (int k : ks) {
-                    if (!divides(tx, d.dims[0]) || !divides(ty, d.dims[1]) || k * C > 64) continue;
+                    if (!divides(tx, d.dims[0]) || !divides(ty, d.dims[1]) || k * C > 64) continue;   // k < 0 passes
                     if (tx < ty / 2 || ty < tx / 4) continue;   // keep near-square, x-wide shapes
                     Tiling t;
                     t.tx = tx; t.ty = ty; t.tz = 1; t.k = k;
@@ -88,7 +91,7 @@ namespace {
 hmc_status time_lattice(hmc_lattice* L, const Tiling& t, float kT, int32_t n_mcs, double* us) {
     HMC_TRY(hmc_set_tiling(L, t.tx, t.ty, t.tz, t.k));
     HMC_TRY(hmc_restore(L));
-    HMC_TRY(hmc_sweep(L, kT, std::min(n_mcs, 2 * t.k), 1));
+    HMC_TRY(hmc_sweep(L, kT, std::min(n_mcs, 2 * std::max(t.k, 1)), 1));
     HMC_TRY(hmc_restore(L));
     hipEvent_t a, b;
     HMC_HIP(hipEventCreate(&a));

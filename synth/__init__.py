@@ -200,6 +200,14 @@ def misorientation_2d_1024():
     return w
 
 
+def moore26_3d_128():
+    """128^3 Moore 26-neighbour (8-colour) int16, 2500 grains (mean volume as
+    schmid_3d_256 / 1.0), energies as schmid_3d_256, kT 0.6, 100 MCS."""
+    w = schmid_3d(side=128, G=2500, seed=3007, n_mcs=100, vseed=13, sseed=13, name="moore26_3d_128")
+    w.nbr = MOORE26
+    return w
+
+
 def stress_3d_512():
     """512^3 VN6 int32 (512 MiB per buffer), 160000 grains (mean volume as
     schmid_3d_256) with energies as schmid_3d_256, kT 0.6, 50 MCS."""

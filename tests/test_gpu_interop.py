@@ -30,7 +30,7 @@ def _tensor_from(arr, dtype):
 
 
 @pytest.mark.parametrize("spin,tdtype", [(hmc.HMC_I16, torch.int16), (hmc.HMC_I32, torch.int32)])
-@pytest.mark.parametrize("k,chunks", [(2, [5]), (4, [3]), (4, [6, 1]), (1, [1, 1, 2])])
+@pytest.mark.parametrize("k,chunks", [(2, [5]), (4, [3]), (4, [6, 1]), (1, [1, 1, 2]), (-3, [1, 2]), (-1, [3])])
 def test_wrapped_tensor_follows_oracle(spin, tdtype, k, chunks):
     dims, Q, vseed, seed, kT = (64, 48), 30, 11, 21, 0.7
     say(f"[gpu] wrap spin={spin} k={k} chunks={chunks}")

@@ -107,11 +107,13 @@ def test_single_grain_never_changes():
 # ------------------------------------------------------ determinism contract
 
 @pytest.mark.parametrize("dims,nbr,tilings", [
-    ((128, 96), hmc.HMC_VN4, [(64, 32, 0, 1), (32, 32, 0, 3), (128, 96, 0, 1), (16, 48, 0, 5), (2, 2, 0, 1)]),
+    ((128, 96), hmc.HMC_VN4, [(64, 32, 0, 1), (32, 32, 0, 3), (128, 96, 0, 1), (16, 48, 0, 5), (2, 2, 0, 1),
+                              (32, 32, 0, -1), (64, 32, 0, -3)]),
     ((38, 20), hmc.HMC_VN4, [(38, 20, 0, 1), (2, 10, 0, 1), (38, 4, 0, 2)]),   # Lx = 2 mod 4: 2-byte rows
-    ((96, 64), hmc.HMC_MOORE8, [(32, 32, 0, 1), (96, 16, 0, 2), (8, 8, 0, 1)]),
-    ((24, 20, 16), hmc.HMC_VN6, [(8, 10, 4, 1), (24, 20, 2, 1), (12, 4, 16, 2), (4, 4, 4, 3)]),
-    ((16, 12, 8), hmc.HMC_MOORE26, [(4, 4, 4, 1), (8, 6, 8, 1), (16, 2, 2, 1)]),
+    ((96, 64), hmc.HMC_MOORE8, [(32, 32, 0, 1), (96, 16, 0, 2), (8, 8, 0, 1), (32, 32, 0, -2), (32, 16, 0, -3)]),
+    ((24, 20, 16), hmc.HMC_VN6, [(8, 10, 4, 1), (24, 20, 2, 1), (12, 4, 16, 2), (4, 4, 4, 3), (8, 10, 4, -1)]),
+    ((16, 12, 8), hmc.HMC_MOORE26, [(4, 4, 4, 1), (8, 6, 8, 1), (16, 2, 2, 1), (4, 4, 4, -2), (8, 6, 8, -4),
+                                    (16, 2, 2, -3)]),
 ])
 def test_result_independent_of_tiling(dims, nbr, tilings):
     Q = 40
