@@ -178,6 +178,29 @@ def sweep_pair(spins, nbr, dims, Jp, B, kT, n_mcs, seed, mcs0=0, proposal=PROP_N
     return s.reshape(src.shape).astype(src.dtype)
 
 
+FIELD_CARRY, FIELD_RECRYSTALLISE = 0, 1
+
+
+def sweep_field(spins, field, rule, nbr, dims, B, kT, n_mcs, seed, mcs0=0, J_fx=65536, threads=1):
+    """As sweep with a per-site bulk field (Eq. (7)'s b_i inside grains,
+    2^-16 units) added to the grain energies B; a swept site takes the field
+    of the neighbour whose spin it adopts (FIELD_CARRY) or zero
+    (FIELD_RECRYSTALLISE).  Returns (spins, field)."""
+    src = np.asarray(spins)
+    s = np.ascontiguousarray(src.astype(np.int32).reshape(-1))
+    e = np.ascontiguousarray(np.asarray(field, dtype=np.int32).reshape(-1).copy())
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
+    d = _dims3(dims)
+    f = lib().orc_sweep_field
+    f.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
+                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.c_uint64, C.c_int32, C.c_uint64, C.c_int]
+    rc = f(_ptr(s, C.c_int32), _ptr(e, C.c_int32), int(rule), int(nbr), _ptr(d, C.c_int32), int(J_fx),
+           _ptr(b, C.c_int32), len(b), float(kT), int(mcs0), int(n_mcs), int(seed), int(threads))
+    if rc != 0:
+        raise ValueError(f"orc_sweep_field failed with {rc}")
+    return s.reshape(src.shape).astype(src.dtype), e.reshape(src.shape)
+
+
 def delta_energy_pair(spins, nbr, dims, Jp, B, i, q_new):
     s = np.ascontiguousarray(np.asarray(spins, dtype=np.int32).reshape(-1))
     b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))

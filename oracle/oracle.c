@@ -260,9 +260,18 @@ int64_t orc_delta_energy_pair(const int32_t *spins, int nbr, const int32_t dims_
  *           trial reads the state as it was when the half step began).
  *
  * Returns 0, or -1 on bad arguments, -2 if an energy change leaves int32. */
+/* Per-site bulk field (Eq. (7)'s b_i varying inside a grain): E_site[i] in
+ * 2^-16 units adds to the grain's B[q_i].  When site i is swept, its field
+ * becomes e_new: with ORC_FIELD_CARRY the value of the neighbour whose spin
+ * it adopts (the overtaking grain's dislocation content is carried into the
+ * swept site, the paper's closing discussion), with ORC_FIELD_RECRYSTALLISE
+ * zero (a dislocation-free, recrystallised site). */
+enum { ORC_FIELD_CARRY = 0, ORC_FIELD_RECRYSTALLISE = 1 };
+
 static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
                       int32_t J_fx, const int32_t *Jp, const int32_t *B, int32_t Q, float kT,
-                      uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
+                      uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads,
+                      int32_t *E_site, int rule)
 {
     int off[26][3];
     int M = orc_offsets(nbr, off);
@@ -270,15 +279,20 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
     int64_t dims[3] = {dims_in[0], dims_in[1], dims_in[2]};
     int64_t N = dims[0] * dims[1] * dims[2];
     uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
-    int32_t *before;
+    int32_t *before, *before_e = NULL;
     int overflow = 0;
     int32_t step;
     int colour;
     if (M < 0 || n_mcs < 0 || Q < 1 || !(kT > 0.0f)) return -1;
     if (N <= 0) return -1;
     if (n_mcs == 0) return 0;
+    if (E_site && proposal != ORC_PROP_NEIGHBOUR) return -1;   /* the carry rule needs a proposing neighbour */
     before = (int32_t *)malloc((size_t)N * sizeof(int32_t));
     if (!before) return -1;
+    if (E_site) {
+        before_e = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+        if (!before_e) { free(before); return -1; }
+    }
     if (threads < 1) threads = 1;
 
     for (step = 0; step < n_mcs; ++step) {
@@ -288,12 +302,13 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
             /* Half step: every trial sees the state at the start of the
              * half step; accepted flips land in `spins` only. */
             memcpy(before, spins, (size_t)N * sizeof(int32_t));
+            if (E_site) memcpy(before_e, E_site, (size_t)N * sizeof(int32_t));
 #pragma omp parallel for num_threads(threads) schedule(static) reduction(| : overflow)
             for (i = 0; i < N; ++i) {
                 int64_t x = i % dims[0], y = (i / dims[0]) % dims[1];
                 int64_t z = i / (dims[0] * dims[1]);
                 uint32_t ctr[4], r[4];
-                int32_t q, q_new;
+                int32_t q, q_new, e_new = 0;
                 int64_t d;
                 if (orc_colour(nbr, x, y, z) != colour) continue;
                 q = before[i];
@@ -301,7 +316,9 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
                 orc_philox4x32_10(ctr, key, r);
                 if (proposal == ORC_PROP_NEIGHBOUR) {
                     int k = (int)(((uint64_t)r[0] * (uint64_t)M) >> 32);
-                    q_new = before[orc_neighbour_index(dims, off, k, x, y, z)];
+                    int64_t j = orc_neighbour_index(dims, off, k, x, y, z);
+                    q_new = before[j];
+                    if (E_site) e_new = rule == ORC_FIELD_CARRY ? before_e[j] : 0;
                 } else {
                     uint32_t s = (uint32_t)(((uint64_t)r[0] * (uint64_t)(Q - 1)) >> 32);
                     q_new = (int32_t)(((int64_t)q + 1 + (int64_t)s) % Q);
@@ -309,12 +326,17 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
                 if (q_new == q) continue;
                 d = Jp ? orc_delta_energy_pair(before, nbr, dims_in, Jp, Q, B, i, q_new)
                        : orc_delta_energy(before, nbr, dims_in, J_fx, B, i, q_new);
+                if (E_site) d += (int64_t)e_new - (int64_t)before_e[i];
                 if (d > INT32_MAX || d < INT32_MIN) { overflow = 1; continue; }
-                if (d <= 0 || r[1] < orc_threshold(d, kT)) spins[i] = q_new;
+                if (d <= 0 || r[1] < orc_threshold(d, kT)) {
+                    spins[i] = q_new;
+                    if (E_site) E_site[i] = e_new;
+                }
             }
         }
     }
     free(before);
+    free(before_e);
     return overflow ? -2 : 0;
 }
 
@@ -322,7 +344,19 @@ int orc_sweep(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3],
               int32_t J_fx, const int32_t *B, int32_t Q, float kT,
               uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
 {
-    return sweep_impl(spins, nbr, proposal, dims_in, J_fx, NULL, B, Q, kT, mcs0, n_mcs, seed, threads);
+    return sweep_impl(spins, nbr, proposal, dims_in, J_fx, NULL, B, Q, kT, mcs0, n_mcs, seed, threads, NULL, 0);
+}
+
+/* As orc_sweep with a per-site bulk field E_site int32[N] (updated in place)
+ * and the rule that sets the field of a swept site (ORC_FIELD_CARRY or
+ * ORC_FIELD_RECRYSTALLISE); neighbour trials only. */
+int orc_sweep_field(int32_t *spins, int32_t *E_site, int rule, int nbr, const int32_t dims_in[3],
+                    int32_t J_fx, const int32_t *B, int32_t Q, float kT,
+                    uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
+{
+    if (!E_site || (rule != ORC_FIELD_CARRY && rule != ORC_FIELD_RECRYSTALLISE)) return -1;
+    return sweep_impl(spins, nbr, ORC_PROP_NEIGHBOUR, dims_in, J_fx, NULL, B, Q, kT, mcs0, n_mcs, seed, threads,
+                      E_site, rule);
 }
 
 /* As orc_sweep with a bond energy per pair of spins: Jp int32[Q*Q],
@@ -332,7 +366,7 @@ int orc_sweep_pair(int32_t *spins, int nbr, int proposal, const int32_t dims_in[
                    uint64_t mcs0, int32_t n_mcs, uint64_t seed, int threads)
 {
     if (!Jp) return -1;
-    return sweep_impl(spins, nbr, proposal, dims_in, 0, Jp, B, Q, kT, mcs0, n_mcs, seed, threads);
+    return sweep_impl(spins, nbr, proposal, dims_in, 0, Jp, B, Q, kT, mcs0, n_mcs, seed, threads, NULL, 0);
 }
 
 /* -------------------------------------------------------------- Voronoi */
