@@ -161,6 +161,28 @@ hmc_status hmc_set_pair_energy(hmc_lattice *L, const int32_t *Jp, int32_t n_grai
 hmc_status hmc_misorientation_energy(const double *euler, int32_t Q, double J_max, double theta_m_deg,
                                      int32_t on_device, int32_t *Jp_out);
 
+/* Per-site bulk field: Eq. (7) gives each site its own bulk energy b_i;
+ * E_site int32[N] (2^-16 units, |E| <= 2^24, host or device per on_device,
+ * copied) adds to the grain energies B[q_i].  When a trial at site i is
+ * accepted the site's field becomes e_new: with HMC_FIELD_CARRY the field of
+ * the neighbour whose spin it adopts (the overtaking grain's dislocation
+ * content moves with the boundary, the reading the paper's closing section
+ * adopts), with HMC_FIELD_RECRYSTALLISE zero (the swept site is
+ * dislocation-free, the alternative it describes).  dE gains
+ * e_new - E_site[i]; acceptance uses T(d) for every d > 0.  Needs neighbour
+ * trials; not combined with pair bond energies; ensembles do not take such
+ * lattices.  The field is checkpointed by hmc_snapshot / hmc_restore.
+ * E_site = NULL removes the field.  Synchronous.  Errors: INVAL (sizes,
+ * rule, trial mode, pair mode, values), RANGE (J_fx M + 2 max|B| +
+ * 2 max|E| >= 2^31), NOMEM, DEVICE. */
+enum { HMC_FIELD_CARRY = 0, HMC_FIELD_RECRYSTALLISE = 1 };
+hmc_status hmc_set_site_energy(hmc_lattice *L, const int32_t *E_site, uint64_t n_sites, int32_t on_device,
+                               int32_t rule);
+
+/* Copy the current per-site field to host int32[N].  Synchronous.
+ * Errors: INVAL, STATE (no field set), DEVICE. */
+hmc_status hmc_get_site_energy(hmc_lattice *L, int32_t *out, uint64_t n_sites);
+
 /* n_mcs Monte Carlo steps of red/black Metropolis (Sec. 4) at temperature
  * kT (the paper's effective temperature alpha_mc with J = 1), drawing from
  * the Philox stream of `seed`.  Steps are numbered from the lattice's MC

@@ -55,6 +55,8 @@ _SIGS = [
     ("hmc_lattice_free", C.c_int32, [C.c_void_p]),
     ("hmc_set_grain_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
     ("hmc_set_pair_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_set_site_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32]),
+    ("hmc_get_site_energy", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64]),
     ("hmc_misorientation_energy", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                               C.c_void_p]),
     ("hmc_sweep", C.c_int32, [C.c_void_p, C.c_float, C.c_int32, C.c_uint64]),
@@ -188,6 +190,24 @@ def hmc_set_pair_energy(h, Jp):
         return
     j = np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
     _check(lib().hmc_set_pair_energy(h, _ptr(j), j.shape[0], 0))
+
+
+HMC_FIELD_CARRY, HMC_FIELD_RECRYSTALLISE = 0, 1
+
+
+def hmc_set_site_energy(h, E_site, rule=HMC_FIELD_CARRY):
+    """Per-site bulk field int32[N] (2^-16 units), or None to remove it."""
+    if E_site is None:
+        _check(lib().hmc_set_site_energy(h, None, 0, 0, 0))
+        return
+    e = np.ascontiguousarray(np.asarray(E_site, dtype=np.int32))
+    _check(lib().hmc_set_site_energy(h, _ptr(e), e.size, 0, int(rule)))
+
+
+def hmc_get_site_energy(h, shape):
+    out = np.empty(shape, dtype=np.int32)
+    _check(lib().hmc_get_site_energy(h, _ptr(out), out.size))
+    return out
 
 
 def hmc_misorientation_energy(euler, J_max, theta_m_deg):
@@ -465,6 +485,12 @@ class Lattice:
 
     def set_pair_energy(self, Jp):
         hmc_set_pair_energy(self.h, Jp)
+
+    def set_site_energy(self, E_site, rule=HMC_FIELD_CARRY):
+        hmc_set_site_energy(self.h, E_site, rule)
+
+    def site_energy(self):
+        return hmc_get_site_energy(self.h, self.shape)
 
     def sweep(self, kT, n_mcs, seed):
         hmc_sweep(self.h, kT, n_mcs, seed)

@@ -132,8 +132,9 @@ struct Table {
 uint32_t threshold_value(int64_t d, float kT);
 hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax,
                        hipStream_t stream);
-// Threshold table T(d) for every d in [0, Dmax] (pair bond energies).
-hmc_status build_pair_table(hmc_lattice* L, float kT);
+// Threshold table T(d) for every d in [0, Dmax] (pair bond energies,
+// per-site field).
+hmc_status build_direct_table(hmc_lattice* L, float kT);
 void free_table(Table& tab);
 
 // ---------------------------------------------------------------- tiling
@@ -197,6 +198,13 @@ struct hmc_lattice_s {
     size_t Tg_bytes = 0;
     uint32_t Tg_kT_bits = 0;
     int32_t Tg_Dmax = -1;
+
+    // per-site bulk field (Eq. (7)'s b_i inside grains), ping-pong with the spins
+    bool field = false;
+    int32_t* d_field[2] = {nullptr, nullptr};
+    int32_t* field_snap = nullptr;
+    int32_t Fmin = 0, Fmax = 0;               // bounds of every value the field can hold
+    uint32_t frule = 0;                       // 0 carry, 1 recrystallise
 };
 
 namespace hmc {

@@ -152,12 +152,14 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     return HMC_OK;
 }
 
-hmc_status build_pair_table(hmc_lattice* L, float kT) {
+hmc_status build_direct_table(hmc_lattice* L, float kT) {
     uint32_t bits;
     std::memcpy(&bits, &kT, sizeof bits);
     // largest possible d: every bond of the new spin at the largest energy,
-    // none of the old, plus the spread of the grain energies
-    const int64_t Dmax = (int64_t)L->M * L->Jp_max + ((int64_t)L->Bmax - L->Bmin);
+    // none of the old, plus the spreads of the grain energies and the field
+    const int64_t bond = L->pair ? L->Jp_max : L->desc.J_fx;
+    const int64_t Dmax = (int64_t)L->M * bond + ((int64_t)L->Bmax - L->Bmin) +
+                         (L->field ? (int64_t)L->Fmax - L->Fmin : 0);
     if (L->d_Tg && L->Tg_kT_bits == bits && L->Tg_Dmax == Dmax) return HMC_OK;
     const size_t bytes = (size_t)(Dmax + 1) * sizeof(uint32_t);
     if (bytes > kTableCapBytes) return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
@@ -208,10 +210,12 @@ hmc_status validate_desc(const hmc_lattice_desc* d, int32_t n_grains) {
     return HMC_OK;
 }
 
-hmc_status check_energy_range(const hmc_lattice* L, int32_t Bmin, int32_t Bmax, int32_t Jbond) {
+hmc_status check_energy_range(const hmc_lattice* L, int32_t Bmin, int32_t Bmax, int32_t Jbond, int32_t Fmin = 0,
+                              int32_t Fmax = 0) {
     const int64_t maxabs = std::max<int64_t>(std::llabs((int64_t)Bmin), std::llabs((int64_t)Bmax));
-    if ((int64_t)Jbond * L->M + 2 * maxabs >= (1ll << 31))
-        return fail(HMC_E_RANGE, "(largest bond energy)*M + 2 max|B| must stay below 2^31");
+    const int64_t fabs_max = std::max<int64_t>(std::llabs((int64_t)Fmin), std::llabs((int64_t)Fmax));
+    if ((int64_t)Jbond * L->M + 2 * maxabs + 2 * fabs_max >= (1ll << 31))
+        return fail(HMC_E_RANGE, "(largest bond energy)*M + 2 max|B| + 2 max|field| must stay below 2^31");
     return HMC_OK;
 }
 
@@ -231,6 +235,9 @@ void destroy(hmc_lattice* L) {
     dev_free(L->d_trials, kTrialSlots * sizeof(unsigned long long));
     dev_free(L->d_count, sizeof(unsigned long long));
     dev_free(L->d_Jp, (size_t)L->Q * (size_t)L->Q * 4);
+    dev_free(L->d_field[0], (size_t)L->N * 4);
+    dev_free(L->d_field[1], (size_t)L->N * 4);
+    dev_free(L->field_snap, (size_t)L->N * 4);
     dev_free(L->d_Tg, L->Tg_bytes);
     free_table(L->table);
     for (auto& e : L->events) {
@@ -396,7 +403,7 @@ hmc_status hmc_set_grain_energy(hmc_lattice* L, const int32_t* B_fx, int32_t n_g
         lo = std::min(lo, v);
         hi = std::max(hi, v);
     }
-    HMC_TRY(check_energy_range(L, lo, hi, bond_max(L)));
+    HMC_TRY(check_energy_range(L, lo, hi, bond_max(L), L->Fmin, L->Fmax));
     HMC_HIP(hipMemcpyAsync(L->dB, h.data(), (size_t)n_grains * 4, hipMemcpyHostToDevice, L->stream));
     HMC_HIP(hipStreamSynchronize(L->stream));
     L->hB.swap(h);
@@ -436,12 +443,72 @@ hmc_status hmc_set_pair_energy(hmc_lattice* L, const int32_t* Jp, int32_t n_grai
             jmax = std::max(jmax, v);
         }
     }
+    if (L->field) return fail(HMC_E_INVAL, "pair bond energies and a per-site field are not combined");
     HMC_TRY(check_energy_range(L, L->Bmin, L->Bmax, jmax));
     if (!L->d_Jp) HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_Jp), QQ * 4, "pair energies"));
     HMC_HIP(hipMemcpyAsync(L->d_Jp, h.data(), QQ * 4, hipMemcpyHostToDevice, L->stream));
     HMC_HIP(hipStreamSynchronize(L->stream));
     L->pair = true;
     L->Jp_max = jmax;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_site_energy(hmc_lattice* L, const int32_t* E_site, uint64_t n_sites, int32_t on_device,
+                               int32_t rule) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    const size_t bytes = (size_t)L->N * 4;
+    if (!E_site) {   // back to grain energies only
+        dev_free(L->d_field[0], bytes);
+        dev_free(L->d_field[1], bytes);
+        dev_free(L->field_snap, bytes);
+        L->d_field[0] = L->d_field[1] = L->field_snap = nullptr;
+        L->field = false;
+        L->Fmin = L->Fmax = 0;
+        return HMC_OK;
+    }
+    if (n_sites != (uint64_t)L->N) return fail(HMC_E_INVAL, "n_sites must equal the lattice's N");
+    if (rule != HMC_FIELD_CARRY && rule != HMC_FIELD_RECRYSTALLISE) return fail(HMC_E_INVAL, "unknown field rule");
+    if (L->desc.proposal != HMC_PROP_NEIGHBOUR)
+        return fail(HMC_E_INVAL, "a per-site field needs neighbour trials (the swept site takes a neighbour's value)");
+    if (L->pair) return fail(HMC_E_INVAL, "pair bond energies and a per-site field are not combined");
+    std::vector<int32_t> h((size_t)L->N);
+    if (on_device) {
+        HMC_HIP(hipMemcpyAsync(h.data(), E_site, bytes, hipMemcpyDeviceToHost, L->stream));
+        HMC_HIP(hipStreamSynchronize(L->stream));
+    } else {
+        std::memcpy(h.data(), E_site, bytes);
+    }
+    int32_t lo = h[0], hi = h[0];
+    for (int32_t v : h) {
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+    }
+    if (lo < -(1 << 24) || hi > (1 << 24)) return fail(HMC_E_INVAL, "field values must lie in [-2^24, 2^24]");
+    if (rule == HMC_FIELD_RECRYSTALLISE) {   // swept sites hold zero
+        lo = std::min(lo, 0);
+        hi = std::max(hi, 0);
+    }
+    HMC_TRY(check_energy_range(L, L->Bmin, L->Bmax, L->desc.J_fx, lo, hi));
+    for (int b = 0; b < 2; ++b)
+        if (!L->d_field[b]) HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->d_field[b]), bytes, "site field"));
+    HMC_HIP(hipMemcpyAsync(L->d_field[L->cur], h.data(), bytes, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    L->field = true;
+    L->Fmin = lo;
+    L->Fmax = hi;
+    L->frule = (uint32_t)rule;
+    L->Tg_Dmax = -1;   // rebuild the threshold table
+    return HMC_OK;
+}
+
+hmc_status hmc_get_site_energy(hmc_lattice* L, int32_t* out, uint64_t n_sites) {
+    g_error.clear();
+    if (!L || !out) return fail(HMC_E_INVAL, "NULL argument");
+    if (!L->field) return fail(HMC_E_STATE, "no per-site field set");
+    if (n_sites != (uint64_t)L->N) return fail(HMC_E_INVAL, "n_sites must equal the lattice's N");
+    HMC_HIP(hipMemcpyAsync(out, L->d_field[L->cur], (size_t)L->N * 4, hipMemcpyDeviceToHost, L->stream));
+    HMC_HIP(hipStreamSynchronize(L->stream));
     return HMC_OK;
 }
 
@@ -528,6 +595,12 @@ hmc_status hmc_snapshot(hmc_lattice* L) {
     const size_t sb = (size_t)L->N * L->spin_bytes;
     if (!L->snap) HMC_TRY(dev_alloc(&L->snap, sb, "snapshot"));
     HMC_HIP(hipMemcpyAsync(L->snap, L->spins[L->cur], sb, hipMemcpyDeviceToDevice, L->stream));
+    if (L->field) {
+        if (!L->field_snap)
+            HMC_TRY(dev_alloc(reinterpret_cast<void**>(&L->field_snap), (size_t)L->N * 4, "field snapshot"));
+        HMC_HIP(hipMemcpyAsync(L->field_snap, L->d_field[L->cur], (size_t)L->N * 4, hipMemcpyDeviceToDevice,
+                               L->stream));
+    }
     L->snap_mcs = L->mcs;
     L->has_snap = true;
     return HMC_OK;
@@ -539,6 +612,9 @@ hmc_status hmc_restore(hmc_lattice* L) {
     if (!L->has_snap) return fail(HMC_E_STATE, "no snapshot taken");
     const size_t sb = (size_t)L->N * L->spin_bytes;
     HMC_HIP(hipMemcpyAsync(L->spins[L->cur], L->snap, sb, hipMemcpyDeviceToDevice, L->stream));
+    if (L->field && L->field_snap)
+        HMC_HIP(hipMemcpyAsync(L->d_field[L->cur], L->field_snap, (size_t)L->N * 4, hipMemcpyDeviceToDevice,
+                               L->stream));
     L->mcs = L->snap_mcs;
     return HMC_OK;
 }
@@ -670,7 +746,8 @@ hmc_status hmc_ensemble_create(hmc_lattice* const* lats, int32_t n, hmc_ensemble
             return fail(HMC_E_INVAL, "ensemble members must share neighbourhood, spin type and trial mode");
         for (int32_t j = 0; j < i; ++j)
             if (lats[j] == lats[i]) return fail(HMC_E_INVAL, "lattice " + std::to_string(i) + " appears twice");
-        if (lats[i]->pair) return fail(HMC_E_INVAL, "ensembles take lattices with the uniform bond energy only");
+        if (lats[i]->pair || lats[i]->field)
+            return fail(HMC_E_INVAL, "ensembles take lattices with uniform bonds and grain energies only");
     }
     hmc_ensemble* E = new hmc_ensemble();
     E->lats.assign(lats, lats + n);

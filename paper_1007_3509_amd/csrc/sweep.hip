@@ -77,8 +77,11 @@ struct LatArgs {
     uint32_t uniform;         // 1: symmetric trial spins
     unsigned long long* trials;   // when not null: kTrialSlots counters of Philox draws (queued trials)
     const int32_t* Jp;        // pair bond energies int32[Q*Q] (pair mode)
-    const uint32_t* Tg;       // pair mode: T(d) for d = 0..Dmax
+    const uint32_t* Tg;       // pair and field modes: T(d) for d = 0..Dmax
     int32_t Dmax;
+    const int32_t* fsrc;      // field mode: per-site bulk energy, read
+    int32_t* fdst;            //   and written (ping-pong with the spins)
+    uint32_t frule;           //   0: a swept site takes the proposing neighbour's field, 1: zero
 };
 
 // Per-launch arguments: the LDS box and its precomputed reciprocals.
@@ -91,6 +94,7 @@ struct RunArgs {
     uint32_t box_off, queue_off, coord_off, grain_off;   // byte offsets in dynamic LDS
     uint32_t m_bx, m_by, m_tx, m_ty;
     uint32_t m_bx4, m_tx4;    // reciprocals of BX / 4 and TX / 4 (vec)
+    uint32_t field_off;       // byte offset of the per-site field box in LDS (field mode)
     uint32_t m_pass[kMaxPasses][2];   // per pass: per-row and rows reciprocals
 };
 
@@ -155,7 +159,7 @@ __device__ __forceinline__ int nbr_offset(uint32_t k, int BX, int BXY) {
 // One tile: stage tile + halo, run g.P colour passes in LDS, write the interior.
 // Ends with every thread past its last LDS access of the tile (callers that
 // process another tile put a barrier before reusing LDS).
-template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair = false>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair = false, bool kField = false>
 __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g, uint32_t tx, uint32_t ty,
                                              uint32_t tz, unsigned char* smem) {
     using Tr = Traits<NBR>;
@@ -166,6 +170,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     uint32_t* tbound = reinterpret_cast<uint32_t*>(smem);
     uint32_t* qcount = reinterpret_cast<uint32_t*>(smem + kHeaderBytes - 16);
     Spin* box = reinterpret_cast<Spin*>(smem + g.box_off);
+    int32_t* fbox = reinterpret_cast<int32_t*>(smem + g.field_off);   // field mode only
     uint32_t* queue = reinterpret_cast<uint32_t*>(smem + g.queue_off);
     uint32_t* gxs = reinterpret_cast<uint32_t*>(smem + g.coord_off);
     uint32_t* gys = gxs + g.BX;
@@ -241,6 +246,15 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             if (e < box_n) box[e] = (Spin)v[j];
         }
     }
+    if constexpr (kField) {
+        for (uint32_t e = tid; e < box_n; e += nthr) {
+            const uint32_t r = fdiv(e, g.m_bx);
+            const uint32_t u = e - __umul24(r, g.BX);
+            const uint32_t w = (D == 3) ? fdiv(r, g.m_by) : 0u;
+            const uint32_t vv = r - __umul24(w, g.BY);
+            fbox[e] = a.fsrc[gxs[u] + a.Lx * (gys[vv] + a.Ly * gzs[w])];
+        }
+    }
     __syncthreads();
 
     int off[M];
@@ -287,11 +301,14 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             const int32_t bq = Bq[q];
             const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
             int32_t qn;
+            int32_t e_new = 0;   // field mode: the swept site's new field
             if (!a.uniform) {
                 const uint32_t k = __umulhi(r.r0, (uint32_t)M);
                 qn = nb[0];
 #pragma unroll
                 for (int kk = 1; kk < M; ++kk) qn = (k == (uint32_t)kk) ? nb[kk] : qn;
+                if constexpr (kField)
+                    e_new = a.frule ? 0 : fbox[idx + nbr_offset<NBR>(k, (int)g.BX, (int)(g.BX * g.BY))];
             } else {
                 qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
                 if (qn >= a.Q) qn -= a.Q;
@@ -317,6 +334,15 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             }
             const int32_t dn = cq - cn;
             const int32_t dB = Bq[qn] - bq;
+            if constexpr (kField) {
+                // per-site field: dE gains e_new - e_i; threshold per d
+                const int32_t d = a.J_fx * dn + dB + (e_new - fbox[idx]);
+                if (d <= 0 || r.r1 < a.Tg[min(d, a.Dmax)]) {
+                    box[idx] = (Spin)qn;
+                    fbox[idx] = e_new;
+                }
+                return;
+            }
             const int32_t d = a.J_fx * dn + dB;
             bool accept = d <= 0;
             if (!accept) {
@@ -457,6 +483,16 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
     // Interior back to global memory: flat over the tile, coalesced rows.
     const uint32_t tile_n = a.TX * a.TY * a.TZ;
     const uint32_t gx0 = gxs[HX];
+    if constexpr (kField) {
+        for (uint32_t e = tid; e < tile_n; e += nthr) {
+            const uint32_t r = fdiv(e, g.m_tx);
+            const uint32_t u = e - __umul24(r, a.TX);
+            const uint32_t w = (D == 3) ? fdiv(r, g.m_ty) : 0u;
+            const uint32_t vv = r - __umul24(w, a.TY);
+            a.fdst[gx0 + u + a.Lx * (gys[H + vv] + a.Ly * gzs[Hz + w])] =
+                fbox[(HX + u) + __umul24(g.BX, (H + vv) + __umul24(g.BY, Hz + w))];
+        }
+    }
     if constexpr (sizeof(Spin) == 2) {
         if (g.vec) {
             const uint32_t tx4 = a.TX >> 2, groups = tile_n >> 2;
@@ -483,7 +519,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 }
 
 // One lattice: one workgroup per tile.
-template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair>
+template <int NBR, typename Spin, bool kGrainsInLds, bool kSwar, bool kPair, bool kField = false>
 __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs g, uint32_t xcd_group) {
     extern __shared__ __align__(16) unsigned char smem[];
     // Consecutive workgroups are spread over the 8 XCDs round-robin; regroup
@@ -494,7 +530,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(LatArgs a, RunArgs
     const uint32_t tx = b % a.ntx;
     const uint32_t ty = (b / a.ntx) % a.nty;
     const uint32_t tz = b / (a.ntx * a.nty);
-    process_tile<NBR, Spin, kGrainsInLds, kSwar, kPair>(a, g, tx, ty, tz, smem);
+    process_tile<NBR, Spin, kGrainsInLds, kSwar, kPair, kField>(a, g, tx, ty, tz, smem);
 }
 
 // Ensemble: persistent workgroups walk the ragged tile table of all lattices.
@@ -522,15 +558,19 @@ ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restr
 }
 
 template <int NBR, bool kSwar>
-const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair) {
+const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair, bool field) {
     if (ensemble) {
-        if (pair) return nullptr;
+        if (pair || field) return nullptr;
         if (spin == HMC_I16)
             return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, true, kSwar>)
                                  : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int16_t, false, kSwar>);
         return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true, false>)
                              : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false, false>);
     }
+    if (field)   // per-site bulk field; grain energies read from global memory
+        return spin == HMC_I16
+                   ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, false, true>)
+                   : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, false, true>);
     if (pair)   // bond energies from the pair table; grain energies read from global memory
         return spin == HMC_I16 ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, true>)
                                : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, true>);
@@ -547,16 +587,17 @@ bool use_swar(int nbr, int spin, uint32_t BX) {
     return spin == HMC_I16 && (nbr == HMC_VN4 || nbr == HMC_VN6) && BX % 4 == 0;
 }
 
-const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar, bool pair = false) {
+const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar, bool pair = false,
+                       bool field = false) {
     switch (nbr) {
     case HMC_VN4:
-        return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble, pair)
-                    : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble, pair);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble, pair);
+        return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble, pair, field)
+                    : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble, pair, field);
+    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble, pair, field);
     case HMC_VN6:
-        return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble, pair)
-                    : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble, pair);
-    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble, pair);
+        return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble, pair, field)
+                    : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble, pair, field);
+    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble, pair, field);
     }
 }
 
@@ -566,10 +607,12 @@ struct Layout {
     bool grains_in_lds;
     uint32_t HX;              // x halo (H, or H rounded up to 4 with vec)
     bool vec;                 // 8-byte staging and store of 16-bit spins
+    size_t field_off;         // per-site field box (field mode)
 };
 
 // LDS layout of one tile: [bucket bounds, queue counters | box | queue | coords | grains].
-Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes, bool vec) {
+Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tiling& t, int passes, bool vec,
+                  bool field = false) {
     Layout o{};
     o.H = (uint32_t)passes;
     o.HX = vec ? (uint32_t)((passes + 3) & ~3) : (uint32_t)passes;
@@ -591,10 +634,12 @@ Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tili
     o.bytes = o.grain_off;
     o.grains_in_lds = false;
     const size_t with_grains = o.grain_off + (size_t)maxQ * 4;
-    if (maxQ <= kLdsGrainLimit && (int64_t)with_grains <= lds_limit_bytes()) {
+    if (!field && maxQ <= kLdsGrainLimit && (int64_t)with_grains <= lds_limit_bytes()) {
         o.grains_in_lds = true;
         o.bytes = with_grains;
     }
+    o.field_off = (o.bytes + 15) / 16 * 16;
+    if (field) o.bytes = o.field_off + elems * 4;   // per-site field box, int32
     return o;
 }
 
@@ -609,10 +654,10 @@ bool vec_ok(const hmc_lattice* L, const Tiling& t) {
 
 Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
     if (vec_ok(L, t)) {
-        const Layout v = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, true);
+        const Layout v = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, true, L->field);
         if ((int64_t)v.bytes <= lds_limit_bytes() && v.BX <= 1023) return v;
     }
-    return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, false);
+    return box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, t, passes, false, L->field);
 }
 
 RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool swar) {
@@ -628,6 +673,7 @@ RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool s
     g.queue_off = (uint32_t)lay.queue_off;
     g.coord_off = (uint32_t)lay.coord_off;
     g.grain_off = (uint32_t)lay.grain_off;
+    g.field_off = (uint32_t)lay.field_off;
     g.m_bx = magic(lay.BX);
     g.m_by = magic(lay.BY);
     g.m_tx = magic((uint32_t)t.tx);
@@ -690,7 +736,8 @@ int largest_even_divisor_at_most(int L, int target) {
     return 2;
 }
 
-hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t maxQ, const int* dims, const Tiling& r) {
+hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t maxQ, const int* dims, const Tiling& r,
+                        bool field) {
     const int sides[3] = {r.tx, r.ty, r.tz};
     for (int ax = 0; ax < ndim; ++ax) {
         if (sides[ax] < 2 || sides[ax] % 2 != 0 || dims[ax] % sides[ax] != 0)
@@ -699,7 +746,7 @@ hmc_status check_tiling(int nbr, int ndim, int C, size_t spin_bytes, int32_t max
     }
     if (r.k == 0 || launch_passes(r, C) > kMaxPasses)
         return fail(HMC_E_INVAL, "colour passes per launch must be in [1, " + std::to_string(kMaxPasses) + "]");
-    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, launch_passes(r, C), false);
+    const Layout lay = box_layout(nbr, ndim, spin_bytes, maxQ, r, launch_passes(r, C), false, field);
     if (lay.BX > 1023 || lay.BY > 1023 || lay.BZ > 1023)
         return fail(HMC_E_INVAL, "tile + halo exceeds 1023 sites along an axis");
     if ((int64_t)lay.bytes > lds_limit_bytes())
@@ -757,14 +804,14 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
                 if (L->ndim == 3 && r.tz == 0) r.tz = largest_even_divisor_at_most(dims[2], d.tz);
                 if (L->ndim == 2) r.tz = 1;
                 if (r.k == 0) r.k = d.k;
-                const Layout lay =
-                    box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, launch_passes(r, L->C), false);
+                const Layout lay = box_layout(L->desc.nbr, L->ndim, L->spin_bytes, L->Q, r, launch_passes(r, L->C),
+                                              false, L->field);
                 if ((int64_t)lay.bytes <= lds_limit_bytes()) break;
             }
         }
     }
     if (L->ndim == 2) r.tz = 1;
-    HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, L->Q, dims, r));
+    HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, L->Q, dims, r, L->field));
     t = r;
     return HMC_OK;
 }
@@ -774,14 +821,16 @@ hmc_status settle_borrowed(hmc_lattice* L) {
     if (!L->borrowed || L->cur == 0) return HMC_OK;
     HMC_HIP(hipMemcpyAsync(L->spins[0], L->spins[1], (size_t)L->N * L->spin_bytes, hipMemcpyDeviceToDevice,
                            L->stream));
+    if (L->field)
+        HMC_HIP(hipMemcpyAsync(L->d_field[0], L->d_field[1], (size_t)L->N * 4, hipMemcpyDeviceToDevice, L->stream));
     L->cur = 0;
     return HMC_OK;
 }
 
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
     if (n_mcs == 0) return HMC_OK;
-    if (L->pair) {
-        HMC_TRY(build_pair_table(L, kT));
+    if (L->pair || L->field) {
+        HMC_TRY(build_direct_table(L, kT));
     } else {
         HMC_TRY(build_table(L->table, kT, L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
         if (L->table.rows > kMaxRows) return fail(HMC_E_INTERNAL, "threshold table has too many rows");
@@ -791,11 +840,12 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     L->tiling = t;
 
     LatArgs a = lat_args(L, t, seed);
-    if (L->pair) {   // the per-row bounds are not used
+    if (L->pair || L->field) {   // threshold per energy change; the per-row bounds are not used
         a.Jp = L->d_Jp;
         a.Tg = L->d_Tg;
         a.Dmax = L->Tg_Dmax;
         a.nbound = 0;
+        a.frule = L->frule;
     }
     const uint32_t ntiles = a.ntx * a.nty * (a.Lz / a.TZ);
     const uint32_t xcd_group = (ntiles % 8 == 0) ? ntiles / 8 : 0u;
@@ -817,9 +867,11 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
-        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair);
+        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair, L->field);
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
+        a.fsrc = L->d_field[L->cur];
+        a.fdst = L->d_field[L->cur ^ 1];
         a.t0 = (uint32_t)(L->mcs + (uint64_t)(gp0 / L->C));
         a.c0 = (uint32_t)(gp0 % L->C);
         uint32_t xg = xcd_group;
@@ -872,7 +924,7 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         E->tiling = t;
     }
     for (hmc_lattice* L : E->lats)
-        HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, maxQ, L->desc.dims, E->tiling));
+        HMC_TRY(check_tiling(L->desc.nbr, L->ndim, L->C, L->spin_bytes, maxQ, L->desc.dims, E->tiling, false));
     // ragged tile table: every tile of every lattice
     std::vector<uint2> tiles;
     for (size_t i = 0; i < E->lats.size(); ++i) {
@@ -908,7 +960,7 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
 hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* seed, int32_t n_mcs) {
     if (n_mcs == 0) return HMC_OK;
     for (const hmc_lattice* L : E->lats)
-        if (L->pair) return fail(HMC_E_STATE, "an ensemble member was given pair bond energies");
+        if (L->pair || L->field) return fail(HMC_E_STATE, "an ensemble member was given pair or per-site energies");
     if (!E->prepared) HMC_TRY(ensemble_prepare(E));
     hmc_lattice* L0 = E->lats[0];
     const int C = L0->C;

@@ -208,6 +208,28 @@ def moore26_3d_128():
     return w
 
 
+def heterogeneous_field(spins, B, amplitude=0.25, period=64.0):
+    """Per-site bulk field varying inside every grain (a stand-in for the
+    stored energy a continuum solve would give): B[q_i] modulated by
+    1 + amplitude * prod_k sin(2 pi x_k / period), rounded to integers
+    (2^-16 units)."""
+    s = np.asarray(spins)
+    grids = np.meshgrid(*[np.arange(n) for n in s.shape], indexing="ij")
+    mod = np.ones(s.shape)
+    for gk in grids:
+        mod = mod * np.sin(2 * np.pi * gk / period)
+    return np.rint(np.asarray(B, dtype=np.float64)[s] * (1.0 + amplitude * mod)).astype(np.int32)
+
+
+def field_2d_1024(rule=0):
+    """schmid_2d_1024 with a per-site field inside the grains (the grain
+    energies modulated by +-25 % with period 64); rule 0 carries the field
+    with the boundary, rule 1 recrystallises swept sites."""
+    w = schmid_2d(name="field_2d_1024" if rule == 0 else "recrystallise_2d_1024")
+    w.extra["field_rule"] = rule
+    return w
+
+
 def stress_3d_512():
     """512^3 VN6 int32 (512 MiB per buffer), 160000 grains (mean volume as
     schmid_3d_256) with energies as schmid_3d_256, kT 0.6, 50 MCS."""
