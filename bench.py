@@ -46,6 +46,8 @@ WORKLOADS = {
     "stress_3d_512": synth.stress_3d_512,
     "misorientation_2d_1024": synth.misorientation_2d_1024,
     "moore26_3d_128": synth.moore26_3d_128,
+    "field_2d_1024": lambda: synth.field_2d_1024(0),
+    "recrystallise_2d_1024": lambda: synth.field_2d_1024(1),
 }
 SPECIAL = ("ensemble_moore8", "learned_3d_256")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}
@@ -86,7 +88,7 @@ def measured_profile(workload, tiling):
     return {k: float(fields[k]) for k in keys[:2] if k in fields}
 
 
-def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
+def cpu_baseline(w, start, n_mcs, budget_s, gpu_check, field=None):
     """The oracle, as it stands, on the same job from the same initial state."""
     import oracle
 
@@ -100,6 +102,13 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check):
 
         def run(n, th):
             return oracle.sweep_pair(start, w.nbr, w.dims, Jp, w.B, w.kT, n, w.sweep_seed, threads=th)
+    elif field is not None:
+        Jp = None
+        zeros = np.zeros(w.n_grains, np.int32)
+
+        def run(n, th):
+            return oracle.sweep_field(start, field, w.extra["field_rule"], w.nbr, w.dims, zeros, w.kT, n,
+                                      w.sweep_seed, threads=th)[0]
     else:
         Jp = None
 
@@ -164,6 +173,12 @@ def main():
     if args.tiling:
         lat.set_tiling(*[int(v) for v in args.tiling.split(",")])
     start = lat.spins()
+    rule = w.extra.get("field_rule")
+    field = None
+    if rule is not None:   # bulk energy per site: the grain energies modulated inside every grain
+        field = synth.heterogeneous_field(start, w.B, 0.25, 64.0)
+        lat.set_grain_energy(np.zeros(w.n_grains, np.int32))
+        lat.set_site_energy(field, rule)
     fb_start = lat.boundary_sites() / w.n_sites
     hmc.hmc_snapshot(lat.h)
     gbin = w.grain_bin if w.n_bins else None
@@ -201,7 +216,8 @@ def main():
     value = total_su / elapsed
     s_bytes = np.dtype(w.spin_dtype).itemsize
     C = w.colours
-    bytes_per_su = (C + 1) * s_bytes
+    # spins (and the per-site field, int32) read for every pass, written for the updated colour
+    bytes_per_su = (C + 1) * (s_bytes + (4 if field is not None else 0))
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     su_per_launch = su / max(launches, 1)
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
@@ -272,7 +288,7 @@ def main():
             lat.sweep(w.kT, sample, w.sweep_seed)
             return lat.spins().astype(np.int32)
         gpu_check.table = lambda: gpu_table
-        out["cpu_baseline"] = cpu_baseline(w, start.astype(np.int32), n_mcs, args.cpu_seconds, gpu_check)
+        out["cpu_baseline"] = cpu_baseline(w, start.astype(np.int32), n_mcs, args.cpu_seconds, gpu_check, field)
     lat.close()
     print(json.dumps(out), flush=True)
 
