@@ -201,6 +201,71 @@ def sweep_field(spins, field, rule, nbr, dims, B, kT, n_mcs, seed, mcs0=0, J_fx=
     return s.reshape(src.shape).astype(src.dtype), e.reshape(src.shape)
 
 
+def nfold(spins, nbr, dims, B, kT, seed, t_end, t_last=0.0, n_events=0, J_fx=65536,
+          proposal=PROP_NEIGHBOUR, max_events=-1):
+    """The n-fold way (rejection-free, continuous-time) counterpart of the
+    Metropolis dynamics of Sec. 3, named in Sec. 1 and Sec. 4 as the
+    alternative to red/black updating: run until t_end (MC steps) from the
+    clock (t_last, n_events).  Returns (spins, t_last, n_events, executed)."""
+    src = np.asarray(spins)
+    s = np.ascontiguousarray(src.astype(np.int32).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
+    d = _dims3(dims)
+    tl = C.c_double(float(t_last))
+    ne = C.c_uint64(int(n_events))
+    f = lib().orc_nfold
+    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
+                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.c_uint64, C.c_double,
+                  C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int64]
+    f.restype = C.c_int64
+    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), int(J_fx), _ptr(b, C.c_int32),
+           len(b), float(kT), int(seed), float(t_end), C.byref(tl), C.byref(ne),
+           int(max_events))
+    if rc < 0:
+        raise ValueError(f"orc_nfold failed with {rc}")
+    return s.reshape(src.shape).astype(src.dtype), tl.value, ne.value, int(rc)
+
+
+def nfold_exponentials(seed, n0, count):
+    """Exp(1) variates of the n-fold way's event streams n0 .. n0+count-1,
+    32.32 fixed point (von Neumann's comparison method)."""
+    out = np.zeros(int(count), dtype=np.uint64)
+    f = lib().orc_nfold_exponentials
+    f.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.POINTER(C.c_uint64)]
+    f(int(seed), int(n0), int(count), _ptr(out, C.c_uint64))
+    return out
+
+
+def nfold_select(w, r):
+    """Index of the entry whose cumulative weight first exceeds r, and the
+    rest of r (the n-fold way's choice of site and slot); (-1, r) if r is
+    not below the total."""
+    a = np.ascontiguousarray(np.asarray(w, dtype=np.uint64))
+    rest = C.c_uint64(0)
+    f = lib().orc_nfold_select
+    f.argtypes = [C.POINTER(C.c_uint64), C.c_int64, C.c_uint64, C.POINTER(C.c_uint64)]
+    f.restype = C.c_int64
+    i = int(f(_ptr(a, C.c_uint64), a.size, int(r), C.byref(rest)))
+    return i, (rest.value if i >= 0 else int(r))
+
+
+def nfold_weights(spins, nbr, dims, B, kT, J_fx=65536, proposal=PROP_NEIGHBOUR):
+    """Integer rate weights w_ik of every slot of every site (N x S)."""
+    s = np.ascontiguousarray(np.asarray(spins, dtype=np.int32).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
+    d = _dims3(dims)
+    S = num_neighbours(nbr) if proposal == PROP_NEIGHBOUR else len(b) - 1
+    out = np.zeros((s.size, S), dtype=np.uint64)
+    f = lib().orc_nfold_weights
+    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
+                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.POINTER(C.c_uint64)]
+    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), int(J_fx), _ptr(b, C.c_int32),
+           len(b), float(kT), _ptr(out, C.c_uint64))
+    if rc < 0:
+        raise ValueError("orc_nfold_weights failed")
+    return out
+
+
 def delta_energy_pair(spins, nbr, dims, Jp, B, i, q_new):
     s = np.ascontiguousarray(np.asarray(spins, dtype=np.int32).reshape(-1))
     b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
