@@ -202,25 +202,32 @@ def sweep_field(spins, field, rule, nbr, dims, B, kT, n_mcs, seed, mcs0=0, J_fx=
 
 
 def nfold(spins, nbr, dims, B, kT, seed, t_end, t_last=0.0, n_events=0, J_fx=65536,
-          proposal=PROP_NEIGHBOUR, max_events=-1):
+          proposal=PROP_NEIGHBOUR, max_events=-1, Jp=None):
     """The n-fold way (rejection-free, continuous-time) counterpart of the
     Metropolis dynamics of Sec. 3, named in Sec. 1 and Sec. 4 as the
     alternative to red/black updating: run until t_end (MC steps) from the
-    clock (t_last, n_events).  Returns (spins, t_last, n_events, executed)."""
+    clock (t_last, n_events).  Jp: optional Q x Q bond energies (Eq. (7)'s
+    J_{q_i,q_n}).  Returns (spins, t_last, n_events, executed)."""
     src = np.asarray(spins)
     s = np.ascontiguousarray(src.astype(np.int32).reshape(-1))
     b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
     d = _dims3(dims)
     tl = C.c_double(float(t_last))
     ne = C.c_uint64(int(n_events))
-    f = lib().orc_nfold
-    f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
-                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.c_uint64, C.c_double,
-                  C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int64]
+    i32p = C.POINTER(C.c_int32)
+    tail = [C.c_int32, C.c_float, C.c_uint64, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int64]
+    if Jp is None:
+        f = lib().orc_nfold
+        f.argtypes = [i32p, C.c_int, C.c_int, i32p, C.c_int32, i32p] + tail
+        bond = int(J_fx)
+    else:
+        jp = np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
+        f = lib().orc_nfold_pair
+        f.argtypes = [i32p, C.c_int, C.c_int, i32p, i32p, i32p] + tail
+        bond = _ptr(jp, C.c_int32)
     f.restype = C.c_int64
-    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), int(J_fx), _ptr(b, C.c_int32),
-           len(b), float(kT), int(seed), float(t_end), C.byref(tl), C.byref(ne),
-           int(max_events))
+    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), bond, _ptr(b, C.c_int32),
+           len(b), float(kT), int(seed), float(t_end), C.byref(tl), C.byref(ne), int(max_events))
     if rc < 0:
         raise ValueError(f"orc_nfold failed with {rc}")
     return s.reshape(src.shape).astype(src.dtype), tl.value, ne.value, int(rc)
@@ -249,18 +256,20 @@ def nfold_select(w, r):
     return i, (rest.value if i >= 0 else int(r))
 
 
-def nfold_weights(spins, nbr, dims, B, kT, J_fx=65536, proposal=PROP_NEIGHBOUR):
+def nfold_weights(spins, nbr, dims, B, kT, J_fx=65536, proposal=PROP_NEIGHBOUR, Jp=None):
     """Integer rate weights w_ik of every slot of every site (N x S)."""
     s = np.ascontiguousarray(np.asarray(spins, dtype=np.int32).reshape(-1))
     b = np.ascontiguousarray(np.asarray(B, dtype=np.int32))
     d = _dims3(dims)
     S = num_neighbours(nbr) if proposal == PROP_NEIGHBOUR else len(b) - 1
     out = np.zeros((s.size, S), dtype=np.uint64)
+    jp = None if Jp is None else np.ascontiguousarray(np.asarray(Jp, dtype=np.int32))
     f = lib().orc_nfold_weights
     f.argtypes = [C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
-                  C.POINTER(C.c_int32), C.c_int32, C.c_float, C.POINTER(C.c_uint64)]
-    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), int(J_fx), _ptr(b, C.c_int32),
-           len(b), float(kT), _ptr(out, C.c_uint64))
+                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.c_float, C.POINTER(C.c_uint64)]
+    rc = f(_ptr(s, C.c_int32), int(nbr), int(proposal), _ptr(d, C.c_int32), int(J_fx),
+           None if jp is None else _ptr(jp, C.c_int32), _ptr(b, C.c_int32), len(b), float(kT),
+           _ptr(out, C.c_uint64))
     if rc < 0:
         raise ValueError("orc_nfold_weights failed")
     return out

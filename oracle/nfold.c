@@ -135,6 +135,7 @@ typedef struct {
     int32_t dims[3];
     int64_t N;
     int32_t J_fx, Q;
+    const int32_t *Jp; /* Q x Q bond energies, or NULL for J_fx on every unlike bond */
     const int32_t *B;
     float kT;
     int32_t *spins;
@@ -142,18 +143,24 @@ typedef struct {
 } nf_lattice;
 
 /* Energy change of Eq. (7) (J(1-delta), each bond once, plus B of the
- * spin) when site i goes from its spin to q_new. */
+ * spin) when site i goes from its spin to q_new; with a pair table the bond
+ * between spins a and b costs Jp[a][b] (zero diagonal). */
 static int64_t nf_delta(const nf_lattice *L, int64_t i, int32_t q_new)
 {
     int32_t q = L->spins[i];
-    int64_t unlike_before = 0, unlike_after = 0;
+    int64_t before = 0, after = 0;
     int k;
     for (k = 0; k < L->M; ++k) {
         int32_t s = L->spins[L->nb[i * L->M + k]];
-        if (s != q) ++unlike_before;
-        if (s != q_new) ++unlike_after;
+        if (L->Jp) {
+            before += L->Jp[(int64_t)q * L->Q + s];
+            after += L->Jp[(int64_t)q_new * L->Q + s];
+        } else {
+            if (s != q) before += L->J_fx;
+            if (s != q_new) after += L->J_fx;
+        }
     }
-    return (int64_t)L->J_fx * (unlike_after - unlike_before) + (int64_t)L->B[q_new] - (int64_t)L->B[q];
+    return after - before + (int64_t)L->B[q_new] - (int64_t)L->B[q];
 }
 
 /* Candidate spin of slot k of site i, or -1 for an empty slot. */
@@ -237,9 +244,9 @@ int64_t orc_nfold_select(const uint64_t *w, int64_t n, uint64_t r, uint64_t *res
  *
  * Returns the number of events executed, or -1 on bad arguments, -2 if an
  * energy change leaves int32. */
-int64_t orc_nfold(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3], int32_t J_fx,
-                  const int32_t *B, int32_t Q, float kT, uint64_t seed, double t_end,
-                  double *t_last, uint64_t *n_events, int64_t max_events)
+static int64_t nfold_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3], int32_t J_fx,
+                          const int32_t *Jp, const int32_t *B, int32_t Q, float kT, uint64_t seed, double t_end,
+                          double *t_last, uint64_t *n_events, int64_t max_events)
 {
     nf_lattice L;
     uint64_t *Wsite, *Wblock, W = 0;
@@ -258,6 +265,7 @@ int64_t orc_nfold(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3
     if ((nbr == 2 || nbr == 3) && L.dims[2] < 3) return -1;
     L.N = (int64_t)L.dims[0] * L.dims[1] * L.dims[2];
     L.J_fx = J_fx;
+    L.Jp = Jp;
     L.Q = Q;
     L.B = B;
     L.kT = kT;
@@ -273,10 +281,17 @@ int64_t orc_nfold(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3
 
     /* every energy change must stay in int32, as in the sweep */
     {
-        int64_t bmin = B[0], bmax = B[0], worst;
+        int64_t bmin = B[0], bmax = B[0], bond = J_fx < 0 ? -(int64_t)J_fx : J_fx, worst, e;
         int32_t q;
         for (q = 1; q < Q; ++q) { if (B[q] < bmin) bmin = B[q]; if (B[q] > bmax) bmax = B[q]; }
-        worst = (int64_t)L.M * (J_fx < 0 ? -(int64_t)J_fx : J_fx) + (bmax - bmin);
+        if (Jp) {
+            bond = 0;
+            for (e = 0; e < (int64_t)Q * Q; ++e) {
+                int64_t v = Jp[e] < 0 ? -(int64_t)Jp[e] : Jp[e];
+                if (v > bond) bond = v;
+            }
+        }
+        worst = (int64_t)L.M * bond + (bmax - bmin);
         if (worst > INT32_MAX) { free(L.nb); free(Wsite); free(Wblock); return -2; }
     }
 
@@ -338,10 +353,29 @@ int64_t orc_nfold(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3
     return done;
 }
 
+int64_t orc_nfold(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3], int32_t J_fx,
+                  const int32_t *B, int32_t Q, float kT, uint64_t seed, double t_end,
+                  double *t_last, uint64_t *n_events, int64_t max_events)
+{
+    return nfold_impl(spins, nbr, proposal, dims_in, J_fx, NULL, B, Q, kT, seed, t_end, t_last, n_events,
+                      max_events);
+}
+
+/* The same run with a bond energy per pair of spins (Eq. (7)'s J_{q_i,q_n},
+ * Jp symmetric with zero diagonal, 2^-16 units). */
+int64_t orc_nfold_pair(int32_t *spins, int nbr, int proposal, const int32_t dims_in[3], const int32_t *Jp,
+                       const int32_t *B, int32_t Q, float kT, uint64_t seed, double t_end,
+                       double *t_last, uint64_t *n_events, int64_t max_events)
+{
+    if (!Jp) return -1;
+    return nfold_impl(spins, nbr, proposal, dims_in, 0, Jp, B, Q, kT, seed, t_end, t_last, n_events,
+                      max_events);
+}
+
 /* Exposed for the tests: the rate of every slot of every site of a state,
- * as the integer weights above (N x S, row-major). */
+ * as the integer weights above (N x S, row-major); Jp may be NULL. */
 int orc_nfold_weights(const int32_t *spins, int nbr, int proposal, const int32_t dims_in[3], int32_t J_fx,
-                      const int32_t *B, int32_t Q, float kT, uint64_t *out)
+                      const int32_t *Jp, const int32_t *B, int32_t Q, float kT, uint64_t *out)
 {
     nf_lattice L;
     int64_t i;
@@ -355,6 +389,7 @@ int orc_nfold_weights(const int32_t *spins, int nbr, int proposal, const int32_t
     memcpy(L.dims, dims_in, sizeof L.dims);
     L.N = (int64_t)L.dims[0] * L.dims[1] * L.dims[2];
     L.J_fx = J_fx;
+    L.Jp = Jp;
     L.Q = Q;
     L.B = B;
     L.kT = kT;

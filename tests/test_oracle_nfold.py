@@ -42,6 +42,16 @@ def _energy(s3, nbr, J, B):
     return J * (tot // 2) + int(np.asarray(B, dtype=np.int64)[s3].sum())
 
 
+def _energy_pair(s3, nbr, Jp, B):
+    """Eq. (7) with a bond energy per pair of spins, every bond once."""
+    tot = 0
+    for dx, dy, dz in OFFS[nbr]:
+        t = np.roll(s3, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
+        tot += int(np.asarray(Jp, dtype=np.int64)[s3, t].sum())
+    assert tot % 2 == 0
+    return tot // 2 + int(np.asarray(B, dtype=np.int64)[s3].sum())
+
+
 def _T(d, kT):
     """floor(2^32 exp(-d / (65536 kT))) with kT rounded to float32 first."""
     x = d / (65536.0 * float(np.float32(kT)))
@@ -49,13 +59,14 @@ def _T(d, kT):
     return 0xFFFFFFFF if v >= 4294967295.0 else int(math.floor(v))
 
 
-def _brute_weights(s3, nbr, J, B, kT, proposal):
+def _brute_weights(s3, nbr, J, B, kT, proposal, Jp=None):
     """Slot weights from energy differences of the full Hamiltonian."""
     Z, Y, X = s3.shape
     Q = len(B)
     S = len(OFFS[nbr]) if proposal == 0 else Q - 1
     out = np.zeros((s3.size, S), dtype=np.uint64)
-    E0 = _energy(s3, nbr, J, B)
+    energy = (lambda u: _energy(u, nbr, J, B)) if Jp is None else (lambda u: _energy_pair(u, nbr, Jp, B))
+    E0 = energy(s3)
     for z in range(Z):
         for y in range(Y):
             for x in range(X):
@@ -71,7 +82,7 @@ def _brute_weights(s3, nbr, J, B, kT, proposal):
                         c = (q + 1 + k) % Q
                     t = s3.copy()
                     t[z, y, x] = c
-                    d = _energy(t, nbr, J, B) - E0
+                    d = energy(t) - E0
                     out[i, k] = (1 << 32) if d <= 0 else _T(d, kT)
     return out
 
@@ -103,6 +114,30 @@ def test_weights_without_bulk_energy_include_zero_changes(orc, nbr, shape):
     want = _brute_weights(s3, nbr, 65536, B, 0.5, 0)
     assert np.array_equal(got, want)
     assert np.count_nonzero(got == (1 << 32)) > 10
+
+
+@pytest.mark.parametrize("nbr,shape", [(0, (1, 6, 8)), (1, (1, 6, 6)), (2, (4, 4, 4))])
+def test_pair_weights_are_rates_of_the_pair_hamiltonian(orc, nbr, shape):
+    rng = np.random.default_rng(70 + nbr)
+    Q = 5
+    s3 = rng.integers(0, Q, size=shape).astype(np.int32)
+    A = np.triu(rng.integers(0, 90000, size=(Q, Q)), 1)
+    Jp = (A + A.T).astype(np.int32)
+    B = rng.integers(-30000, 30000, size=Q).astype(np.int32)
+    dims = (shape[2], shape[1], shape[0])
+    got = orc.nfold_weights(s3, nbr, dims, B, 0.6, Jp=Jp)
+    assert np.array_equal(got, _brute_weights(s3, nbr, 0, B, 0.6, 0, Jp=Jp))
+
+
+def test_uniform_pair_table_is_the_uniform_run(orc):
+    rng = np.random.default_rng(71)
+    Q, dims = 6, (12, 10)
+    s = rng.integers(0, Q, size=(10, 12)).astype(np.int32)
+    B = rng.integers(-20000, 20000, size=Q).astype(np.int32)
+    Jp = (65536 * (1 - np.eye(Q))).astype(np.int32)
+    a = orc.nfold(s, 0, dims, B, 0.7, seed=4, t_end=2.5)
+    b = orc.nfold(s, 0, dims, B, 0.7, seed=4, t_end=2.5, Jp=Jp)
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
 
 
 def test_selection_is_the_first_cumulative_weight_above_r(orc):
