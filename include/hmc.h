@@ -291,6 +291,56 @@ hmc_status hmc_ensemble_autotune(hmc_ensemble *E, const float *kT, const uint64_
 /* Release the ensemble (not its members).  NULL is a no-op. */
 hmc_status hmc_ensemble_free(hmc_ensemble *E);
 
+/* ---------------------------------------------------------- n-fold way
+ * The rejection-free alternative to red/black updating named in Sec. 1 and
+ * Sec. 4 (Bortz, Kalos, Lebowitz 1975; Hassold and Holm 1993): the single-
+ * site Metropolis process of Sec. 3 in continuous time.  Every site attempts
+ * at rate one per MC step; an attempt proposes one of S slots (NEIGHBOUR:
+ * the M neighbour spins, S = M; UNIFORM: q+1..q+Q-1 mod Q, S = Q-1) and is
+ * accepted with the sweep's rule.  Slot k of site i fires at rate
+ * w_ik / (S 2^32) per MC step, w_ik = 2^32 if d <= 0, T(d) if d > 0 (T and d
+ * as above; a neighbour slot holding the site's own spin has weight 0), W is
+ * the sum of all weights, and events happen one at a time:
+ *   - event n draws Philox4x32-10 blocks with key (lo32(seed), hi32(seed))
+ *     and counter (lo32(n), hi32(n), 0x4E464F57, j), j = 0, 1, ..., read
+ *     word by word;
+ *   - words 0, 1 give u = w0 + 2^32 w1 and the rank r = floor(u W / 2^64);
+ *     the event is the site whose cumulative weight (sites in index order)
+ *     first exceeds r, then, with r reduced by the sites before it, the slot
+ *     whose cumulative weight first exceeds the rest;
+ *   - the following words give E, an Exp(1) variate in 32.32 fixed point by
+ *     von Neumann's comparison method (a trial takes u0 and the length n of
+ *     the strictly decreasing run u0 > u1 > ... it starts, the word ending
+ *     the run used up; odd n returns K + u0/2^32, even n adds one to K;
+ *     runs cut at 64 words, K at 64);
+ *   - the event happens at t_last + (E S) / W (double, one rounding per
+ *     operation); if that is beyond the end of the call it is not executed
+ *     and the next call draws it again from the same counter, so splitting
+ *     a run between calls changes nothing.  A lattice with W = 0 has no event.
+ * Each lattice carries its own clock (t_now, t_last, n_events), starting at
+ * zero, separate from the MC-step counter of hmc_sweep; snapshots include it.
+ * The lattice's spins live in LDS during a call (N * spin size + N/8 bytes
+ * must fit the device's LDS, 160 KiB on MI355X: up to about 75 000 int16 or
+ * 38 000 int32 sites); per-site fields are not supported (HMC_E_STATE);
+ * the UNIFORM mode needs uniform bonds and Q <= 65.  Calls are synchronous. */
+
+/* Advance one lattice by mcs MC steps of continuous time. */
+hmc_status hmc_nfold(hmc_lattice *L, float kT, double mcs, uint64_t seed);
+
+/* Advance n distinct lattices by mcs MC steps each in one launch per event
+ * budget, one wave per lattice; kT[n], seed[n] per lattice.  The lattices
+ * share device, neighbourhood, spin type, trial mode and bond model (uniform
+ * or pair table); sizes, grain counts and energies may differ.  The result
+ * of each lattice equals its own hmc_nfold run. */
+hmc_status hmc_nfold_batch(hmc_lattice *const *lats, int32_t n, const float *kT, double mcs,
+                           const uint64_t *seed);
+
+/* Clock of the n-fold way: the time the lattice has been advanced to, the
+ * time of its last event and the number of events so far. */
+hmc_status hmc_nfold_clock(const hmc_lattice *L, double *t_now, double *t_last, uint64_t *n_events);
+/* Set the clock (a restart from saved spins); t_last <= t_now, both finite. */
+hmc_status hmc_nfold_set_clock(hmc_lattice *L, double t_now, double t_last, uint64_t n_events);
+
 /* ------------------------------------------------------------ autotuner
  * Time candidate tilings (tile sides x MC steps per launch) of hmc_sweep on
  * a scratch lattice with this descriptor, n_grains Voronoi grains and zero

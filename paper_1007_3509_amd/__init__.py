@@ -84,6 +84,11 @@ _SIGS = [
     ("hmc_ensemble_synchronize", C.c_int32, [C.c_void_p]),
     ("hmc_ensemble_autotune", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     ("hmc_ensemble_free", C.c_int32, [C.c_void_p]),
+    ("hmc_nfold", C.c_int32, [C.c_void_p, C.c_float, C.c_double, C.c_uint64]),
+    ("hmc_nfold_batch", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p]),
+    ("hmc_nfold_clock", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_uint64)]),
+    ("hmc_nfold_set_clock", C.c_int32, [C.c_void_p, C.c_double, C.c_double, C.c_uint64]),
     ("hmc_autotune", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_float, C.c_int32, C.c_char_p,
                                  C.c_void_p, C.POINTER(C.c_double)]),
     ("hmc_tuning_load", C.c_int32, [C.c_char_p, C.POINTER(C.c_int32)]),
@@ -349,6 +354,29 @@ def hmc_ensemble_free(E):
     _check(lib().hmc_ensemble_free(E))
 
 
+def hmc_nfold(h, kT, mcs, seed):
+    _check(lib().hmc_nfold(h, float(kT), float(mcs), int(seed)))
+
+
+def hmc_nfold_batch(lats, kT, mcs, seed):
+    arr, n = _handles(lats)
+    k = np.ascontiguousarray(np.asarray(kT, dtype=np.float32).reshape(-1))
+    s = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64).reshape(-1))
+    if k.size != n or s.size != n:
+        raise ValueError("one kT and one seed per lattice")
+    _check(lib().hmc_nfold_batch(arr, n, _ptr(k), float(mcs), _ptr(s)))
+
+
+def hmc_nfold_clock(h):
+    t_now, t_last, ne = C.c_double(), C.c_double(), C.c_uint64()
+    _check(lib().hmc_nfold_clock(h, C.byref(t_now), C.byref(t_last), C.byref(ne)))
+    return t_now.value, t_last.value, ne.value
+
+
+def hmc_nfold_set_clock(h, t_now, t_last, n_events):
+    _check(lib().hmc_nfold_set_clock(h, float(t_now), float(t_last), int(n_events)))
+
+
 def hmc_autotune(desc, n_grains, kT, n_mcs, cache_path=None):
     out = np.zeros(4, dtype=np.int32)
     us = C.c_double()
@@ -494,6 +522,17 @@ class Lattice:
 
     def sweep(self, kT, n_mcs, seed):
         hmc_sweep(self.h, kT, n_mcs, seed)
+
+    def nfold(self, kT, mcs, seed):
+        """Advance by mcs MC steps of continuous time with the n-fold way."""
+        hmc_nfold(self.h, kT, mcs, seed)
+
+    def nfold_clock(self):
+        """(t_now, t_last, n_events) of the n-fold way."""
+        return hmc_nfold_clock(self.h)
+
+    def set_nfold_clock(self, t_now, t_last, n_events):
+        hmc_nfold_set_clock(self.h, t_now, t_last, n_events)
 
     def spins(self):
         return hmc_get_spins(self.h, self.shape, self.dtype)

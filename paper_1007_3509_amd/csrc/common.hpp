@@ -205,6 +205,13 @@ struct hmc_lattice_s {
     int32_t* field_snap = nullptr;
     int32_t Fmin = 0, Fmax = 0;               // bounds of every value the field can hold
     uint32_t frule = 0;                       // 0 carry, 1 recrystallise
+
+    // clock of the n-fold way (continuous time in MC steps, separate from mcs)
+    double nf_t_now = 0.0;                    // time the lattice has been advanced to
+    double nf_t_last = 0.0;                   // time of the last executed event
+    uint64_t nf_events = 0;                   // events executed (the event counter of the RNG)
+    double snap_nf_t_now = 0.0, snap_nf_t_last = 0.0;
+    uint64_t snap_nf_events = 0;
 };
 
 namespace hmc {
@@ -244,5 +251,11 @@ hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas
 hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins);
 int lds_limit_bytes();
+hmc_status settle_borrowed(hmc_lattice* L);
+
+// n-fold way (nfold.hip): LDS a lattice needs, and a batch run of lattices
+// that share neighbourhood, spin type, trial mode and bond model.
+size_t nfold_lds_bytes(int64_t N, size_t spin_bytes);
+hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT, double mcs, const uint64_t* seed);
 
 }  // namespace hmc

@@ -313,7 +313,7 @@ using namespace hmc;
 
 extern "C" {
 
-int32_t hmc_abi_version(void) { return 2; }
+int32_t hmc_abi_version(void) { return 3; }
 
 const char* hmc_last_error(void) { return g_error.c_str(); }
 
@@ -602,6 +602,9 @@ hmc_status hmc_snapshot(hmc_lattice* L) {
                                L->stream));
     }
     L->snap_mcs = L->mcs;
+    L->snap_nf_t_now = L->nf_t_now;
+    L->snap_nf_t_last = L->nf_t_last;
+    L->snap_nf_events = L->nf_events;
     L->has_snap = true;
     return HMC_OK;
 }
@@ -616,6 +619,9 @@ hmc_status hmc_restore(hmc_lattice* L) {
         HMC_HIP(hipMemcpyAsync(L->d_field[L->cur], L->field_snap, (size_t)L->N * 4, hipMemcpyDeviceToDevice,
                                L->stream));
     L->mcs = L->snap_mcs;
+    L->nf_t_now = L->snap_nf_t_now;
+    L->nf_t_last = L->snap_nf_t_last;
+    L->nf_events = L->snap_nf_events;
     return HMC_OK;
 }
 
@@ -791,6 +797,63 @@ hmc_status hmc_ensemble_get_tiling(hmc_ensemble* E, int32_t* out4) {
     out4[1] = E->tiling.ty;
     out4[2] = E->tiling.tz;
     out4[3] = E->tiling.k;
+    return HMC_OK;
+}
+
+hmc_status hmc_nfold_batch(hmc_lattice* const* lats, int32_t n, const float* kT, double mcs, const uint64_t* seed) {
+    g_error.clear();
+    if (!lats || !kT || !seed) return fail(HMC_E_INVAL, "NULL argument");
+    if (n < 1) return fail(HMC_E_INVAL, "n must be >= 1");
+    if (!(mcs >= 0.0) || !std::isfinite(mcs)) return fail(HMC_E_INVAL, "mcs must be finite and >= 0");
+    const hmc_lattice* L0 = lats[0];
+    if (!L0) return fail(HMC_E_INVAL, "lattice 0 is NULL");
+    const int limit = lds_limit_bytes();
+    for (int32_t b = 0; b < n; ++b) {
+        const hmc_lattice* L = lats[b];
+        const std::string who = "lattice " + std::to_string(b);
+        if (!L) return fail(HMC_E_INVAL, who + " is NULL");
+        for (int32_t c = 0; c < b; ++c)
+            if (lats[c] == L) return fail(HMC_E_INVAL, who + " appears twice in the batch");
+        if (L->device != L0->device) return fail(HMC_E_INVAL, who + " is on another device");
+        if (L->desc.nbr != L0->desc.nbr || L->desc.spin != L0->desc.spin || L->desc.proposal != L0->desc.proposal ||
+            L->pair != L0->pair)
+            return fail(HMC_E_INVAL, who + ": a batch shares neighbourhood, spin type, trial mode and bond model");
+        if (L->field) return fail(HMC_E_STATE, who + ": the n-fold way takes per-grain bulk energies only");
+        if (L->desc.proposal == HMC_PROP_UNIFORM && (L->pair || L->Q > 65))
+            return fail(HMC_E_INVAL, who + ": the symmetric trial mode of the n-fold way needs uniform bonds and Q <= 65");
+        if (!(kT[b] > 0.0f) || !std::isfinite(kT[b]))
+            return fail(HMC_E_INVAL, "kT[" + std::to_string(b) + "] must be positive and finite");
+        if (!std::isfinite(L->nf_t_now + mcs)) return fail(HMC_E_INVAL, who + ": clock would overflow");
+        const size_t need = nfold_lds_bytes(L->N, L->spin_bytes);
+        if (need > (size_t)limit)
+            return fail(HMC_E_RANGE, who + ": the n-fold way keeps a lattice in LDS; " + std::to_string(L->N) +
+                                         " sites need " + std::to_string(need) + " bytes, the device has " +
+                                         std::to_string(limit));
+    }
+    return launch_nfold(lats, n, kT, mcs, seed);
+}
+
+hmc_status hmc_nfold(hmc_lattice* L, float kT, double mcs, uint64_t seed) {
+    return hmc_nfold_batch(&L, 1, &kT, mcs, &seed);
+}
+
+hmc_status hmc_nfold_clock(const hmc_lattice* L, double* t_now, double* t_last, uint64_t* n_events) {
+    g_error.clear();
+    if (!L || !t_now || !t_last || !n_events) return fail(HMC_E_INVAL, "NULL argument");
+    *t_now = L->nf_t_now;
+    *t_last = L->nf_t_last;
+    *n_events = L->nf_events;
+    return HMC_OK;
+}
+
+hmc_status hmc_nfold_set_clock(hmc_lattice* L, double t_now, double t_last, uint64_t n_events) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (!std::isfinite(t_now) || !std::isfinite(t_last) || t_last > t_now)
+        return fail(HMC_E_INVAL, "the clock needs finite times with t_last <= t_now");
+    L->nf_t_now = t_now;
+    L->nf_t_last = t_last;
+    L->nf_events = n_events;
     return HMC_OK;
 }
 
