@@ -49,7 +49,7 @@ WORKLOADS = {
     "field_2d_1024": lambda: synth.field_2d_1024(0),
     "recrystallise_2d_1024": lambda: synth.field_2d_1024(1),
 }
-SPECIAL = ("ensemble_moore8", "learned_3d_256")
+SPECIAL = ("ensemble_moore8", "learned_3d_256", "nfold_ensemble_128")
 NBR_NAME = {0: "VN4", 1: "Moore8", 2: "VN6", 3: "Moore26"}
 
 
@@ -161,6 +161,8 @@ def main():
         return bench_ensemble(args, hmc)
     if args.workload == "learned_3d_256":
         return bench_learned(args, hmc)
+    if args.workload == "nfold_ensemble_128":
+        return bench_nfold(args, hmc)
     w = WORKLOADS[args.workload]()
     n_mcs = args.mcs or w.n_mcs
     lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
@@ -358,6 +360,132 @@ def bench_ensemble(args, hmc):
            "mcs_per_step": n_mcs, "tiling": list(tiling)},
           one_by_one={"value": su / res["one_by_one"], "ms_per_step": res["one_by_one"] * 1e3},
           speedup_vs_one_by_one=res["one_by_one"] / res["ensemble"], ensemble_equals_one_by_one=same)
+
+
+def nfold_profile():
+    """Per-launch SQ_INSTS_VALU of the n-fold kernel from the committed
+    rocprofv3 summary, or None when the kernel source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "nfold_kernel_nfold_ensemble_128.md")
+    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "nfold.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    return float(fields["valu_wave_instructions_per_launch"]) if "valu_wave_instructions_per_launch" in fields else None
+
+
+def bench_nfold(args, hmc):
+    """The n-fold way (rejection-free, continuous time) on 1024 VN4 128^2
+    lattices at kT 0.25, one batch call (one wave per lattice), against the
+    same lattices advanced by the same MC time with red/black sweeps in one
+    ensemble call; the oracle's n-fold way on a sample of the lattices as the
+    CPU baseline, bit-exact with the GPU on that sample."""
+    import oracle
+
+    members = synth.nfold_ensemble_128()
+    mcs = float(args.mcs or members[0].n_mcs)
+    lats, starts = [], []
+    for w in members:
+        lat = hmc.Lattice(w.dims, w.nbr, w.n_grains, voronoi_seed=w.voronoi_seed, spin=w.spin)
+        lat.set_grain_energy(w.B)
+        starts.append(lat.spins().astype(np.int32))
+        hmc.hmc_snapshot(lat.h)
+        lats.append(lat)
+    kT = np.array([w.kT for w in members], np.float32)
+    seeds = np.array([w.sweep_seed for w in members], np.uint64)
+    total_sites = sum(w.n_sites for w in members)
+
+    def restore():
+        for lat in lats:
+            hmc.hmc_restore(lat.h)
+
+    def nf_step():
+        restore()
+        hmc.hmc_nfold_batch(lats, kT, mcs, seeds)   # synchronous
+
+    for _ in range(args.warmup):
+        nf_step()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nf_step()
+    nf_s = (time.perf_counter() - t0) / args.steps
+    clocks = [lat.nfold_clock() for lat in lats]
+    events = sum(c[2] for c in clocks)
+    # kernel duration: HIP events bound to each n-fold dispatch, one replay
+    hmc.hmc_profile(lats[0].h, True)
+    hmc.hmc_profile_read(lats[0].h)
+    nf_step()
+    kernel_ms, launches, _ = hmc.hmc_profile_read(lats[0].h)
+    hmc.hmc_profile(lats[0].h, False)
+    finals = [lat.spins().astype(np.int32) for lat in lats]
+
+    # red/black sweeps over the same lattices and MC time
+    E = hmc.hmc_ensemble_create(lats)
+
+    def rb_step():
+        restore()
+        hmc.hmc_ensemble_sweep(E, kT, seeds, int(round(mcs)))
+        hmc.hmc_ensemble_synchronize(E)
+
+    for _ in range(args.warmup):
+        rb_step()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rb_step()
+    rb_s = (time.perf_counter() - t0) / args.steps
+    hmc.hmc_ensemble_free(E)
+
+    site_mcs = total_sites * mcs
+    valu = nfold_profile()
+    kernel_s = kernel_ms / 1e3 / max(launches, 1)
+    out = {
+        "metric": "Potts site-MC-steps/s with the n-fold way, 1024-lattice batch, 1 MI355X, bit-exact vs oracle",
+        "value": site_mcs / nf_s, "unit": "site-MC-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": nf_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "nfold_ensemble_128", "lattices": len(members), "lattice": "128x128",
+                   "neighbourhood": "VN4", "grains": 200, "kT": float(kT[0]), "mcs_per_step": mcs},
+        "events_per_step": events,
+        "events_per_s": events / nf_s,
+        "roofline": {
+            "bound": "alu",
+            "achieved": valu / kernel_s / 1e12 * 64 if valu else None,
+            "peak": 157.3, "unit": "TOP/s (VALU lane operations)",
+            "frac": valu / (kernel_s * VALU_ISSUE_PER_S) if valu else None,
+            "traffic": None,
+            "kernel": "nfold_kernel", "avg_launch_us": kernel_s * 1e6, "launches": launches,
+            "latency_per_event_us": kernel_ms * 1e3 / max(max(c[2] for c in clocks), 1),
+            "note": "one dependent chain of events per wave: latency-bound; frac = SQ_INSTS_VALU from profiles/ "
+                    "(null if the kernel changed) against 256 CUs x 2.4 GHz x 1 VALU wave instruction per cycle",
+        },
+        "red_black_same_lattices": {"value": site_mcs / rb_s, "ms_per_step": rb_s * 1e3,
+                                    "note": "hmc_ensemble_sweep over the same 1024 lattices for the same MC steps"},
+    }
+    if not args.no_cpu_baseline:
+        # single-core oracle on whole lattices, as many as the budget allows
+        t0 = time.perf_counter()
+        done, exact = 0, True
+        while done < len(members) and (time.perf_counter() - t0) < args.cpu_seconds:
+            w = members[done]
+            s, t_last, ne, _ = oracle.nfold(starts[done], w.nbr, w.dims, w.B, w.kT, w.sweep_seed, mcs)
+            exact = exact and bool(np.array_equal(s, finals[done])) and (t_last, ne) == clocks[done][1:]
+            done += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done * members[0].n_sites * mcs / dt, "unit": "site-MC-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {done} of {len(members)} lattices, whole {mcs:g}-MCS runs, "
+                                         f"{dt:.1f} s", "gpu_bit_exact_on_sample": exact}
+    for lat in lats:
+        lat.close()
+    print(json.dumps(out), flush=True)
 
 
 def bench_learned(args, hmc):

@@ -65,6 +65,7 @@ struct NfLat {
     NfClock* clock;
     double t_end;
     uint32_t Lx, Ly, Lz, N;
+    uint32_t mx, my;             // ceil(2^32 / Lx), ceil(2^32 / Ly): division by multiply-high
     int32_t Q, J_fx, Dmax, S;
     uint32_t k0, k1;
 };
@@ -93,51 +94,95 @@ __host__ __device__ inline NfLevels nf_levels(uint32_t N) {
     return v;
 }
 
+// LDS of one lattice: spins (16-byte aligned), the tree levels and root
+// (uint64), the grain energies (int32).
 __host__ __device__ inline size_t nf_spin_bytes_lds(uint32_t N, size_t spin_bytes) {
     return ((size_t)N * spin_bytes + 15) & ~(size_t)15;
 }
 
-inline size_t nf_lds_bytes(uint32_t N, size_t spin_bytes) {
+inline size_t nf_lds_bytes(uint32_t N, size_t spin_bytes, int32_t Q) {
     const NfLevels lv = nf_levels(N);
-    return nf_spin_bytes_lds(N, spin_bytes) + 8 * ((size_t)lv.total + 1);
+    return nf_spin_bytes_lds(N, spin_bytes) + 8 * ((size_t)lv.total + 1) + 4 * (size_t)Q;
 }
 
 // ------------------------------------------------------------------ device
 
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t u = __shfl_up(v, (unsigned)o, 64);
-        if (lane >= o) v += u;
-    }
+// A 64-bit value moved across lanes by one DPP pattern; lanes without a
+// source (or outside row_mask) read 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl, kRowMask, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), kCtrl, kRowMask, 0xF, true);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP (no LDS round trips):
+// shifts by 1, 2, 4, 8 inside each row of 16, then the last lane of row 0
+// and 2 added to rows 1 and 3, then the last lane of row 1 to rows 2 and 3.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    v += dpp64<0x111, 0xF>(v);    // row_shr:1
+    v += dpp64<0x112, 0xF>(v);    // row_shr:2
+    v += dpp64<0x114, 0xF>(v);    // row_shr:4
+    v += dpp64<0x118, 0xF>(v);    // row_shr:8
+    v += dpp64<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp64<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
     return v;
 }
 
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+__device__ __forceinline__ uint64_t lane_value64(uint64_t v, int src) {
+    return ((uint64_t)lane_value((uint32_t)(v >> 32), src) << 32) | lane_value((uint32_t)v, src);
+}
+
+// Sum over the wave, in every lane.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) { return lane_value64(wave_incl_scan(v), 63); }
+
 // First lane whose inclusive sum exceeds r (-1 if none), and r reduced by
 // the sum of the lanes before it.
-__device__ __forceinline__ int wave_pick(uint64_t v, int lane, uint64_t& r) {
-    const uint64_t incl = wave_incl_scan(v, lane);
+__device__ __forceinline__ int wave_pick(uint64_t v, uint64_t& r) {
+    const uint64_t incl = wave_incl_scan(v);
     const unsigned long long m = __ballot(incl > r);
     if (m == 0ull) return -1;
     const int c = __ffsll((long long)m) - 1;
-    r -= __shfl(incl - v, c, 64);
+    r -= lane_value64(incl - v, c);
     return c;
 }
 
-struct NfWords {               // the words of one event's Philox stream
-    uint32_t n_lo, n_hi, k0, k1, j;
-    uint32_t b0, b1, b2, b3;
-    int used;
+// The words of one event's Philox stream.  Lanes 0..3 compute blocks 0..3
+// side by side (16 words: almost every event needs fewer); words beyond
+// them come from one further block at a time.
+struct NfWords {
+    uint32_t n_lo, n_hi, k0, k1;
+    uint32_t o0, o1, o2, o3;     // lane l: block l & 3
+    uint32_t e0, e1, e2, e3;     // the current block beyond the first four
+    int w;                       // next word (uniform)
+    __device__ void start(uint64_t n, uint32_t key0, uint32_t key1, int lane) {
+        n_lo = (uint32_t)n;
+        n_hi = (uint32_t)(n >> 32);
+        k0 = key0;
+        k1 = key1;
+        uint32_t o[4];
+        philox4x32_10(n_lo, n_hi, kNfTag, (uint32_t)(lane & 3), k0, k1, o);
+        o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
+        e0 = e1 = e2 = e3 = 0u;
+        w = 0;
+    }
     __device__ uint32_t next() {
-        if (used == 4) {
-            uint32_t o[4];
-            philox4x32_10(n_lo, n_hi, kNfTag, j++, k0, k1, o);
-            b0 = o[0]; b1 = o[1]; b2 = o[2]; b3 = o[3];
-            used = 0;
+        const int idx = w++;
+        const int c = idx & 3;
+        if (idx < 16) {
+            const uint32_t v = c == 0 ? o0 : c == 1 ? o1 : c == 2 ? o2 : o3;
+            return lane_value(v, idx >> 2);
         }
-        const uint32_t w = used == 0 ? b0 : used == 1 ? b1 : used == 2 ? b2 : b3;
-        ++used;
-        return w;
+        if (c == 0) {
+            uint32_t o[4];
+            philox4x32_10(n_lo, n_hi, kNfTag, (uint32_t)(idx >> 2), k0, k1, o);
+            e0 = o[0]; e1 = o[1]; e2 = o[2]; e3 = o[3];
+        }
+        return c == 0 ? e0 : c == 1 ? e1 : c == 2 ? e2 : e3;
     }
 };
 
@@ -177,26 +222,46 @@ __device__ __forceinline__ uint32_t nf_neighbour(const NfLat& a, uint32_t x, uin
     return xn + a.Lx * (yn + a.Ly * zn);
 }
 
+// Coordinates of site j: floor(j / L) = mulhi(j, ceil(2^32 / L)), exact
+// while j * L < 2^32 (the host checks N * Lx and N * Ly).
+__device__ __forceinline__ void nf_coords(const NfLat& a, uint32_t j, uint32_t& x, uint32_t& y, uint32_t& z) {
+    const uint32_t yz = __umulhi(j, a.mx);
+    x = j - yz * a.Lx;
+    z = __umulhi(yz, a.my);
+    y = yz - z * a.Ly;
+}
+
 template <int NBR>
 constexpr int nf_M() {
     return NBR == HMC_VN4 ? 4 : NBR == HMC_MOORE8 ? 8 : NBR == HMC_VN6 ? 6 : 26;
 }
 
+template <int NBR>
+__device__ __forceinline__ uint32_t nf_neighbour_of(const NfLat& a, uint32_t j, int k) {
+    uint32_t x, y, z;
+    nf_coords(a, j, x, y, z);
+    uint32_t out = j;
+#pragma unroll
+    for (int m = 0; m < nf_M<NBR>(); ++m)
+        if (m == k) out = nf_neighbour<NBR>(a, x, y, z, m);
+    return out;
+}
+
 // Spin of the site and of its M neighbours.
 template <int NBR, typename Spin>
 __device__ __forceinline__ int32_t nf_gather(const Spin* s, const NfLat& a, uint32_t j, int32_t* nb) {
-    const uint32_t x = j % a.Lx;
-    const uint32_t yz = j / a.Lx;
-    const uint32_t y = yz % a.Ly;
-    const uint32_t z = yz / a.Ly;
+    uint32_t x, y, z;
+    nf_coords(a, j, x, y, z);
 #pragma unroll
     for (int k = 0; k < nf_M<NBR>(); ++k) nb[k] = (int32_t)s[nf_neighbour<NBR>(a, x, y, z, k)];
     return (int32_t)s[j];
 }
 
-// Weight of moving a site with spin q and neighbour spins nb to spin c != q.
+// Weight of moving a site with spin q and neighbour spins nb to spin c != q;
+// B is the LDS copy of the grain energies.
 template <int NBR, bool kPair>
-__device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, int32_t q, int32_t c, const int32_t* nb) {
+__device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, const int32_t* B, int32_t q, int32_t c,
+                                                   const int32_t* nb) {
     constexpr int M = nf_M<NBR>();
     int64_t d;
     if constexpr (kPair) {
@@ -215,35 +280,42 @@ __device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, int32_t q, in
         }
         d = (int64_t)a.J_fx * (cq - cc);   // unlike bonds after minus before
     }
-    d += (int64_t)a.B[c] - (int64_t)a.B[q];
+    d += (int64_t)B[c] - (int64_t)B[q];
     if (d <= 0) return 1ull << 32;
     return (uint64_t)a.Tg[d < a.Dmax ? d : a.Dmax];
 }
 
-// Candidate spin of slot k (-1 if the slot is empty).
-template <bool kUniform>
-__device__ __forceinline__ int32_t nf_candidate(const NfLat& a, int32_t q, const int32_t* nb, int k) {
-    if constexpr (kUniform) {
-        int32_t c = q + 1 + k;
-        return c >= a.Q ? c - a.Q : c;
-    } else {
-        return nb[k] == q ? -1 : nb[k];
-    }
+// Candidate spin of slot k in the symmetric trial mode.
+__device__ __forceinline__ int32_t nf_uniform_candidate(const NfLat& a, int32_t q, int k) {
+    const int32_t c = q + 1 + k;
+    return c >= a.Q ? c - a.Q : c;
 }
 
+// Weight of site j; in the neighbour mode `only` < 0 counts every slot,
+// otherwise slot `only` alone (its candidate returned in cand, -1 if empty).
 template <int NBR, typename Spin, bool kUniform, bool kPair>
-__device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, uint32_t j) {
+__device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t* B, uint32_t j, int only,
+                                   int32_t& cand) {
     int32_t nb[nf_M<NBR>()];
     const int32_t q = nf_gather<NBR>(s, a, j, nb);
     uint64_t w = 0;
+    cand = -1;
     if constexpr (kUniform) {
-        for (int k = 0; k < a.S; ++k) w += nf_slot_weight<NBR, kPair>(a, q, nf_candidate<true>(a, q, nb, k), nb);
+        for (int k = 0; k < a.S; ++k) w += nf_slot_weight<NBR, kPair>(a, B, q, nf_uniform_candidate(a, q, k), nb);
     } else {
 #pragma unroll
-        for (int k = 0; k < nf_M<NBR>(); ++k)
-            if (nb[k] != q) w += nf_slot_weight<NBR, kPair>(a, q, nb[k], nb);
+        for (int k = 0; k < nf_M<NBR>(); ++k) {
+            if (k == only) cand = nb[k] == q ? -1 : nb[k];
+            if ((only < 0 || k == only) && nb[k] != q) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+        }
     }
     return w;
+}
+
+template <int NBR, typename Spin, bool kUniform, bool kPair>
+__device__ __forceinline__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t* B, uint32_t j) {
+    int32_t unused;
+    return nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, j, -1, unused);
 }
 
 template <int NBR, typename Spin, bool kUniform, bool kPair>
@@ -254,19 +326,23 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
     NfClock* clk = a.clock;
     if (clk->state != kNfRunning) return;
 
+    constexpr int M = nf_M<NBR>();
+    static_assert(M < 32, "slot lanes and site lanes share the wave");
     const NfLevels lv = nf_levels(a.N);
     Spin* s = reinterpret_cast<Spin*>(nf_lds);
     uint64_t* tree = reinterpret_cast<uint64_t*>(nf_lds + nf_spin_bytes_lds(a.N, sizeof(Spin)));
     uint64_t* root = tree + lv.total;
+    int32_t* B = reinterpret_cast<int32_t*>(root + 1);
 
     const Spin* gs = static_cast<const Spin*>(a.spins);
     for (uint32_t i = (uint32_t)lane; i < a.N; i += kNfThreads) s[i] = gs[i];
+    for (int32_t q = lane; q < a.Q; q += kNfThreads) B[q] = a.B[q];
     __syncthreads();
     // level 1: the weight of every run of 64 sites
     for (uint32_t b = 0; b < lv.n[1]; ++b) {
         const uint32_t j = b * 64u + (uint32_t)lane;
-        const uint64_t w = j < a.N ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, j) : 0ull;
-        const uint64_t tot = __shfl(wave_incl_scan(w, lane), 63, 64);
+        const uint64_t w = j < a.N ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, j) : 0ull;
+        const uint64_t tot = wave_sum(w);
         if (lane == 0) tree[lv.off[1] + b] = tot;
     }
     __syncthreads();
@@ -276,7 +352,7 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
         for (uint32_t b = 0; b < lv.n[L]; ++b) {
             const uint32_t c = b * 64u + (uint32_t)lane;
             const uint64_t v = c < lv.n[L - 1] ? tree[lv.off[L - 1] + c] : 0ull;
-            const uint64_t tot = __shfl(wave_incl_scan(v, lane), 63, 64);
+            const uint64_t tot = wave_sum(v);
             if (lane == 0) tree[lv.off[L] + b] = tot;
         }
         __syncthreads();
@@ -290,7 +366,7 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
                 oT = lv.off[L];
             }
         const uint64_t v = (uint32_t)lane < nT ? tree[oT + lane] : 0ull;
-        const uint64_t tot = __shfl(wave_incl_scan(v, lane), 63, 64);
+        const uint64_t tot = wave_sum(v);
         if (lane == 0) *root = tot;
     }
     __syncthreads();
@@ -298,14 +374,14 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
     double t_last = clk->t_last;
     uint64_t n = clk->n_events;
     int32_t state = kNfRunning;
-    constexpr int M = nf_M<NBR>();
     for (int64_t done = 0; done < max_events; ++done) {
         const uint64_t W = *root;
         if (W == 0ull) {
             state = kNfNoEvent;
             break;
         }
-        NfWords wd{(uint32_t)n, (uint32_t)(n >> 32), a.k0, a.k1, 0u, 0u, 0u, 0u, 0u, 4};
+        NfWords wd;
+        wd.start(n, a.k0, a.k1, lane);
         uint64_t u = wd.next();
         u |= (uint64_t)wd.next() << 32;
         const uint64_t E = nf_exponential(wd);
@@ -323,58 +399,55 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
             if (L > lv.T || !ok) continue;
             const uint32_t c = p * 64u + (uint32_t)lane;
             const uint64_t v = c < lv.n[L] ? tree[lv.off[L] + c] : 0ull;
-            const int pick = wave_pick(v, lane, r);
-            ok = pick >= 0;
-            p = p * 64u + (uint32_t)(ok ? pick : 0);
+            const int pick = wave_pick(v, r);
+            ok = pick >= 0 && p * 64u + (uint32_t)pick < lv.n[L];
+            p = ok ? p * 64u + (uint32_t)pick : 0u;
         }
-        int32_t q = 0, nb[M];
-        int32_t cnew = -1;
         uint32_t site = 0;
         if (ok) {
             const uint32_t j = p * 64u + (uint32_t)lane;
-            const uint64_t w = j < a.N ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, j) : 0ull;
-            const int pick = wave_pick(w, lane, r);
-            ok = pick >= 0;
-            site = p * 64u + (uint32_t)(pick < 0 ? 0 : pick);
+            const uint64_t w = j < a.N ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, j) : 0ull;
+            const int pick = wave_pick(w, r);
+            ok = pick >= 0 && p * 64u + (uint32_t)pick < a.N;
+            site = ok ? p * 64u + (uint32_t)pick : 0u;
         }
-        if (ok) {
-            // the slot: lane k takes slot k of the chosen site
-            q = nf_gather<NBR>(s, a, site, nb);
-            uint64_t w = 0;
-            int32_t cand = -1;
-            if (lane < a.S) {
-                if constexpr (kUniform) {
-                    cand = nf_candidate<true>(a, q, nb, lane);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < M; ++k)
-                        if (k == lane) cand = nf_candidate<false>(a, q, nb, k);
-                }
-                if (cand >= 0) w = nf_slot_weight<NBR, kPair>(a, q, cand, nb);
+        // lanes 32..32+M: the site and its M neighbours, whose weights change
+        const int aff = lane - 32;
+        const bool act = aff >= 0 && aff <= M;
+        const uint32_t ja = aff >= 1 && aff <= M ? nf_neighbour_of<NBR>(a, site, aff - 1) : site;
+        int32_t cnew = -1;
+        uint64_t before = 0;
+        if constexpr (kUniform) {
+            if (ok) {   // lane k takes slot k of the chosen site
+                int32_t nb[M];
+                const int32_t q = nf_gather<NBR>(s, a, site, nb);
+                const int32_t cand = lane < a.S ? nf_uniform_candidate(a, q, lane) : -1;
+                const uint64_t w = cand >= 0 ? nf_slot_weight<NBR, kPair>(a, B, q, cand, nb) : 0ull;
+                const int pick = wave_pick(w, r);
+                ok = pick >= 0;
+                cnew = (int32_t)lane_value((uint32_t)cand, pick < 0 ? 0 : pick);
             }
-            const int pick = wave_pick(w, lane, r);
+            before = act ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, ja) : 0ull;
+        } else if (ok) {
+            // one pass: lanes k < M weigh slot k of the chosen site, the site
+            // lanes weigh every slot of their site (before the flip)
+            int32_t cand = -1;
+            const uint64_t w = nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, act ? ja : site,
+                                                                          act ? -1 : lane, cand);
+            before = act ? w : 0ull;
+            const int pick = wave_pick(lane < M ? w : 0ull, r);
             ok = pick >= 0;
-            cnew = __shfl(cand, pick < 0 ? 0 : pick, 64);
-            ok = ok && cnew >= 0;
+            cnew = (int32_t)lane_value((uint32_t)cand, pick < 0 ? 0 : pick);
         }
+        ok = ok && cnew >= 0 && cnew < a.Q;
         if (!ok) {   // the tree disagrees with the spins: stop and report
             state = kNfBroken;
             break;
         }
-        // the site and its M neighbours change weight
-        uint32_t ja = site;
-        const bool act = lane <= M;
-        if (lane >= 1 && lane <= M) {
-            const uint32_t x = site % a.Lx, yz = site / a.Lx;
-#pragma unroll
-            for (int k = 0; k < M; ++k)
-                if (k == lane - 1) ja = nf_neighbour<NBR>(a, x, yz % a.Ly, yz / a.Ly, k);
-        }
-        const uint64_t before = act ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, ja) : 0ull;
         __syncthreads();
         if (lane == 0) s[site] = (Spin)cnew;
         __syncthreads();
-        const uint64_t after = act ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, ja) : 0ull;
+        const uint64_t after = act ? nf_site_weight<NBR, Spin, kUniform, kPair>(s, a, B, ja) : 0ull;
         if (act && after != before) {
             const unsigned long long delta = (unsigned long long)(after - before);
             uint32_t idx = ja;
@@ -421,12 +494,69 @@ const void* nf_kernel_ptr(int nbr, int spin, bool uniform, bool pair) {
 }
 
 // Launch arguments and clocks of a batch, kept per device between calls.
+// T(d) for d = 0..Dmax at one kT.  Lattices of a batch that share kT share
+// one table sized for the largest Dmax among them: the values depend on d
+// and kT only, and one table stays in L2 where a table per lattice would not.
+struct NfTable {
+    uint32_t kT_bits = 0;
+    int64_t Dmax = -1;
+    uint32_t* dev = nullptr;
+    size_t bytes = 0;
+    uint64_t used = 0;
+};
+constexpr size_t kNfTablesKept = 4;                // tables kept per device between calls
+constexpr size_t kNfTableCapBytes = 64ull << 20;
+
 struct NfBuffers {
     void* d_lats = nullptr;
     size_t lats_bytes = 0;
     NfClock* d_clocks = nullptr;
     size_t clocks_bytes = 0;
+    std::vector<NfTable> tables;
+    uint64_t tick = 0;
 };
+
+// A table covering d = 0..Dmax at kT (a cached one with a larger Dmax
+// serves as well); returns its device pointer and its Dmax.  A table used
+// since call_tick (by an earlier lattice of the same call) is never evicted.
+hmc_status nf_table(NfBuffers& b, float kT, int64_t Dmax, hipStream_t st, uint64_t call_tick, const uint32_t*& out,
+                    int32_t& out_Dmax) {
+    uint32_t bits;
+    std::memcpy(&bits, &kT, sizeof bits);
+    for (NfTable& t : b.tables)
+        if (t.dev && t.kT_bits == bits && t.Dmax >= Dmax) {
+            t.used = ++b.tick;
+            out = t.dev;
+            out_Dmax = (int32_t)t.Dmax;
+            return HMC_OK;
+        }
+    const size_t bytes = (size_t)(Dmax + 1) * sizeof(uint32_t);
+    if (Dmax > INT32_MAX || bytes > kNfTableCapBytes)
+        return fail(HMC_E_RANGE, "n-fold way: threshold table would need " + std::to_string(bytes) + " bytes");
+    NfTable* slot = nullptr;
+    if (b.tables.size() >= kNfTablesKept)
+        for (NfTable& t : b.tables)
+            if (t.used < call_tick && (!slot || t.used < slot->used)) slot = &t;
+    if (!slot) {
+        b.tables.emplace_back();
+        slot = &b.tables.back();
+    }
+    dev_free(slot->dev, slot->bytes);
+    *slot = NfTable{};
+    std::vector<uint32_t> host((size_t)Dmax + 1);
+    host[0] = 0xFFFFFFFFu;   // d <= 0 never reads the table
+    for (int64_t d = 1; d <= Dmax; ++d) host[(size_t)d] = threshold_value(d, kT);
+    HMC_TRY(dev_alloc(reinterpret_cast<void**>(&slot->dev), bytes, "n-fold threshold table"));
+    slot->bytes = bytes;
+    HMC_HIP(hipMemcpyAsync(slot->dev, host.data(), bytes, hipMemcpyHostToDevice, st));
+    HMC_HIP(hipStreamSynchronize(st));
+    slot->kT_bits = bits;
+    slot->Dmax = Dmax;
+    slot->used = ++b.tick;
+    out = slot->dev;
+    out_Dmax = (int32_t)Dmax;
+    return HMC_OK;
+}
 std::mutex g_nf_mutex;
 std::vector<NfBuffers> g_nf_buffers;
 
@@ -453,7 +583,7 @@ hmc_status nf_buffers(int device, size_t n, NfBuffers*& out) {
 
 }  // namespace
 
-size_t nfold_lds_bytes(int64_t N, size_t spin_bytes) { return nf_lds_bytes((uint32_t)N, spin_bytes); }
+size_t nfold_lds_bytes(int64_t N, size_t spin_bytes, int32_t Q) { return nf_lds_bytes((uint32_t)N, spin_bytes, Q); }
 
 hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT, double mcs, const uint64_t* seed) {
     hmc_lattice* L0 = lats[0];
@@ -461,32 +591,55 @@ hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT
     size_t lds = 0;
     std::vector<NfLat> args((size_t)count);
     std::vector<NfClock> clocks((size_t)count);
+    // the largest energy change of each lattice, and of each temperature
+    std::vector<int64_t> Dmax((size_t)count);
+    std::vector<std::pair<uint32_t, int64_t>> groups;   // (kT bits, largest Dmax)
+    for (int32_t b = 0; b < count; ++b) {
+        const hmc_lattice* L = lats[b];
+        const int64_t bond = L->pair ? L->Jp_max : L->desc.J_fx;
+        Dmax[(size_t)b] = (int64_t)L->M * bond + ((int64_t)L->Bmax - L->Bmin);
+        uint32_t bits;
+        std::memcpy(&bits, &kT[b], sizeof bits);
+        bool found = false;
+        for (auto& g : groups)
+            if (g.first == bits) {
+                g.second = std::max(g.second, Dmax[(size_t)b]);
+                found = true;
+            }
+        if (!found) groups.emplace_back(bits, Dmax[(size_t)b]);
+    }
+    std::lock_guard<std::mutex> lock(g_nf_mutex);
+    NfBuffers* buf = nullptr;
+    HMC_TRY(nf_buffers(L0->device, (size_t)count, buf));
+    const uint64_t call_tick = buf->tick + 1;
     for (int32_t b = 0; b < count; ++b) {
         hmc_lattice* L = lats[b];
         HMC_HIP(hipStreamSynchronize(L->stream));
-        HMC_TRY(build_direct_table(L, kT[b]));
         NfLat& a = args[(size_t)b];
+        uint32_t bits;
+        std::memcpy(&bits, &kT[b], sizeof bits);
+        int64_t gmax = Dmax[(size_t)b];
+        for (const auto& g : groups)
+            if (g.first == bits) gmax = g.second;
+        HMC_TRY(nf_table(*buf, kT[b], gmax, L0->stream, call_tick, a.Tg, a.Dmax));
         a.spins = L->spins[L->cur];
         a.B = L->dB;
-        a.Tg = L->d_Tg;
         a.Jp = L->pair ? L->d_Jp : nullptr;
         a.t_end = L->nf_t_now + mcs;
         a.Lx = (uint32_t)L->desc.dims[0];
         a.Ly = (uint32_t)L->desc.dims[1];
         a.Lz = (uint32_t)(L->ndim == 3 ? L->desc.dims[2] : 1);
         a.N = (uint32_t)L->N;
+        a.mx = (uint32_t)(((1ull << 32) + a.Lx - 1) / a.Lx);
+        a.my = (uint32_t)(((1ull << 32) + a.Ly - 1) / a.Ly);
         a.Q = L->Q;
         a.J_fx = L->desc.J_fx;
-        a.Dmax = L->Tg_Dmax;
         a.S = uniform ? L->Q - 1 : L->M;
         a.k0 = (uint32_t)(seed[b] & 0xFFFFFFFFu);
         a.k1 = (uint32_t)(seed[b] >> 32);
         clocks[(size_t)b] = NfClock{L->nf_t_last, (unsigned long long)L->nf_events, kNfRunning, 0};
-        lds = std::max(lds, nf_lds_bytes(a.N, L->spin_bytes));
+        lds = std::max(lds, nf_lds_bytes(a.N, L->spin_bytes, L->Q));
     }
-    std::lock_guard<std::mutex> lock(g_nf_mutex);
-    NfBuffers* buf = nullptr;
-    HMC_TRY(nf_buffers(L0->device, (size_t)count, buf));
     for (int32_t b = 0; b < count; ++b) args[(size_t)b].clock = buf->d_clocks + b;
     hipStream_t st = L0->stream;
     HMC_HIP(hipMemcpyAsync(buf->d_lats, args.data(), args.size() * sizeof(NfLat), hipMemcpyHostToDevice, st));

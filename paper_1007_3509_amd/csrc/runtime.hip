@@ -824,11 +824,16 @@ hmc_status hmc_nfold_batch(hmc_lattice* const* lats, int32_t n, const float* kT,
         if (!(kT[b] > 0.0f) || !std::isfinite(kT[b]))
             return fail(HMC_E_INVAL, "kT[" + std::to_string(b) + "] must be positive and finite");
         if (!std::isfinite(L->nf_t_now + mcs)) return fail(HMC_E_INVAL, who + ": clock would overflow");
-        const size_t need = nfold_lds_bytes(L->N, L->spin_bytes);
+        const size_t need = nfold_lds_bytes(L->N, L->spin_bytes, L->Q);
         if (need > (size_t)limit)
-            return fail(HMC_E_RANGE, who + ": the n-fold way keeps a lattice in LDS; " + std::to_string(L->N) +
-                                         " sites need " + std::to_string(need) + " bytes, the device has " +
+            return fail(HMC_E_RANGE, who + ": the n-fold way keeps a lattice and its grain energies in LDS; " +
+                                         std::to_string(L->N) + " sites and " + std::to_string(L->Q) +
+                                         " grains need " + std::to_string(need) + " bytes, the device has " +
                                          std::to_string(limit));
+        // coordinates by multiply-high are exact while j * Lx and j * Ly stay below 2^32
+        if ((uint64_t)L->N * (uint64_t)L->desc.dims[0] >= (1ull << 32) ||
+            (uint64_t)L->N * (uint64_t)L->desc.dims[1] >= (1ull << 32))
+            return fail(HMC_E_RANGE, who + ": lattice too large for the n-fold way");
     }
     return launch_nfold(lats, n, kT, mcs, seed);
 }

@@ -236,6 +236,20 @@ def stress_3d_512():
     return schmid_3d(side=512, G=160000, seed=3005, n_mcs=50, vseed=9, sseed=9, name="stress_3d_512", spin=I32)
 
 
+def nfold_ensemble_128(count=1024, seed=6006, n_mcs=20):
+    """A batch for the n-fold way at low temperature: `count` VN4 128^2
+    lattices (int16), 200 Voronoi grains each, grain energies as
+    schmid_2d_1024 (E = 0.2 m, m in [0.27, 0.5]), kT 0.25, n_mcs MC steps of
+    continuous time; Voronoi seed 60000+j, event seed 6000+j."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out: List[Workload] = []
+    for j in range(count):
+        m = 0.27 + 0.23 * rng.random(200)
+        out.append(Workload(f"nfold_ensemble_128[{j}]", (128, 128), VN4, I16, 200, 0.25, n_mcs, 60000 + j,
+                            6000 + j, quantise(0.2 * m), m=m))
+    return out
+
+
 def ensemble_moore8(count=64, seed=4004, n_mcs=1000):
     rng = np.random.Generator(np.random.PCG64(seed))
     sides = rng.choice(np.array([128, 256, 512, 1024]), size=count)

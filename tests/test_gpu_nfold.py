@@ -212,3 +212,32 @@ def test_nfold_argument_checks():
         with pytest.raises(hmc.HmcError, match="per-grain"):
             a.nfold(0.5, 1.0, 1)
         assert a.nfold_clock() == (0.0, 0.0, 0)
+
+
+def test_nfold_batch_with_many_temperatures():
+    """More temperatures in one batch than threshold tables kept between
+    calls, twice with other temperatures: every lattice keeps its own table."""
+    lats, starts, Bs = [], [], []
+    try:
+        for k in range(7):
+            lat = hmc.Lattice((24, 20 + 2 * k), hmc.HMC_VN4, 10 + k, voronoi_seed=300 + k)
+            B = _energies(10 + k, 400 + k)
+            lat.set_grain_energy(B)
+            lats.append(lat)
+            Bs.append(B)
+        for rnd, base in enumerate((0.3, 0.55)):
+            starts = [lat.spins().astype(np.int32) for lat in lats]
+            clocks = [lat.nfold_clock() for lat in lats]
+            kTs = [base + 0.05 * k for k in range(7)]
+            seeds = [50 + k for k in range(7)]
+            say(f"[gpu] nfold batch round {rnd}: kT {kTs}")
+            hmc.hmc_nfold_batch(lats, kTs, 1.0, seeds)
+            for k, lat in enumerate(lats):
+                t_end = clocks[k][0] + 1.0
+                want, w_last, w_ne, _ = oracle.nfold(starts[k], hmc.HMC_VN4, lat.dims, Bs[k], kTs[k], seeds[k], t_end,
+                                                     t_last=clocks[k][1], n_events=clocks[k][2])
+                assert np.array_equal(lat.spins().astype(np.int32), want), (rnd, k)
+                assert lat.nfold_clock() == (t_end, w_last, w_ne), (rnd, k)
+    finally:
+        for lat in lats:
+            lat.close()
