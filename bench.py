@@ -363,8 +363,9 @@ def bench_ensemble(args, hmc):
 
 
 def nfold_profile():
-    """Per-launch SQ_INSTS_VALU of the n-fold kernel from the committed
-    rocprofv3 summary, or None when the kernel source changed since."""
+    """Per-launch SQ_INSTS_VALU and scaled HBM bytes of the n-fold kernel
+    from the committed rocprofv3 summary, or None when the kernel source
+    changed since."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "nfold_kernel_nfold_ensemble_128.md")
@@ -379,7 +380,8 @@ def nfold_profile():
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != sha:
         return None
-    return float(fields["valu_wave_instructions_per_launch"]) if "valu_wave_instructions_per_launch" in fields else None
+    return {k: float(fields[k]) for k in ("valu_wave_instructions_per_launch", "traffic_bytes_per_launch")
+            if k in fields}
 
 
 def bench_nfold(args, hmc):
@@ -444,8 +446,10 @@ def bench_nfold(args, hmc):
     hmc.hmc_ensemble_free(E)
 
     site_mcs = total_sites * mcs
-    valu = nfold_profile()
+    prof = nfold_profile() or {}
+    valu = prof.get("valu_wave_instructions_per_launch")
     kernel_s = kernel_ms / 1e3 / max(launches, 1)
+    peak_lane = VALU_ISSUE_PER_S * 64 / 1e12   # VALU lane-instructions/s, 1 wave instruction per CU per cycle
     out = {
         "metric": "Potts site-MC-steps/s with the n-fold way, 1024-lattice batch, 1 MI355X, bit-exact vs oracle",
         "value": site_mcs / nf_s, "unit": "site-MC-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -457,14 +461,15 @@ def bench_nfold(args, hmc):
         "events_per_s": events / nf_s,
         "roofline": {
             "bound": "alu",
-            "achieved": valu / kernel_s / 1e12 * 64 if valu else None,
-            "peak": 157.3, "unit": "TOP/s (VALU lane operations)",
-            "frac": valu / (kernel_s * VALU_ISSUE_PER_S) if valu else None,
-            "traffic": None,
+            "achieved": valu * 64 / kernel_s / 1e12 if valu else None,
+            "peak": peak_lane, "unit": "T VALU lane-instructions/s",
+            "frac": valu * 64 / kernel_s / 1e12 / peak_lane if valu else None,
+            "traffic": prof.get("traffic_bytes_per_launch"),
             "kernel": "nfold_kernel", "avg_launch_us": kernel_s * 1e6, "launches": launches,
             "latency_per_event_us": kernel_ms * 1e3 / max(max(c[2] for c in clocks), 1),
-            "note": "one dependent chain of events per wave: latency-bound; frac = SQ_INSTS_VALU from profiles/ "
-                    "(null if the kernel changed) against 256 CUs x 2.4 GHz x 1 VALU wave instruction per cycle",
+            "note": "one dependent chain of events per wave, four waves per CU (LDS): latency-bound.  achieved = "
+                    "SQ_INSTS_VALU x 64 lanes per launch from profiles/ (null if the kernel changed) over the "
+                    "launch; peak = 256 CUs x 64 lanes x 2.4 GHz (one VALU wave instruction per CU per cycle)",
         },
         "red_black_same_lattices": {"value": site_mcs / rb_s, "ms_per_step": rb_s * 1e3,
                                     "note": "hmc_ensemble_sweep over the same 1024 lattices for the same MC steps"},
