@@ -125,9 +125,13 @@ struct Traits<HMC_MOORE26> {
     static constexpr int M = 26, C = 8, D = 3;
 };
 
+// a mod L for a box coordinate: a lies within a few periods of [0, L) (the
+// halo is at most a few sides), so a 32-bit add or subtract settles it.
 __device__ __forceinline__ uint32_t wrap_coord(int64_t a, uint32_t L) {
-    int64_t r = a % (int64_t)L;
-    return (uint32_t)(r < 0 ? r + L : r);
+    int32_t r = (int32_t)a;
+    while (r < 0) r += (int32_t)L;
+    while (r >= (int32_t)L) r -= (int32_t)L;
+    return (uint32_t)r;
 }
 
 // floor(f / d) = umulhi(f, m) with m = floor(2^32 / d) + 1, exact whenever
@@ -370,10 +374,14 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             const uint32_t totalS = nseg * Wy * Wz;
             const uint32_t plane = g.BX * g.BY;
             const uint32_t pbase = (px + py + pz) & 1u;
-            for (uint32_t f0 = wave * kWave; f0 < totalS; f0 += nthr) {
-                const uint32_t f = f0 + lane;
-                bool pa = false, pb = false;
-                uint32_t qa = 0, qb = 0;
+            // two words per lane and round: half the rounds, one LDS atomic
+            // per wave for all four candidate fields
+            for (uint32_t f0 = wave * kWave; f0 < totalS; f0 += 2 * nthr) {
+                bool pa[2] = {false, false}, pb[2] = {false, false};
+                uint32_t qa[2] = {0u, 0u}, qb[2] = {0u, 0u};
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                const uint32_t f = f0 + j * nthr + lane;
                 if (f < totalS) {
                     const uint32_t rr = fdiv(f, m_row);
                     const uint32_t sg = s_lo + (f - __umul24(rr, nseg));
@@ -400,19 +408,26 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     }
                     const uint32_t k = (c ^ (v + w + pbase)) & 1u;   // first colour-c field
                     const uint32_t ua = u0 + k, ub = u0 + k + 2;
-                    pa = ua >= lox && ua < g.BX - lox && ((x >> (16 * k)) & 0xFFFFull) != 0;
-                    pb = ub >= lox && ub < g.BX - lox && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
-                    qa = ua | (v << 10) | (w << 20);
-                    qb = ub | (v << 10) | (w << 20);
+                    pa[j] = ua >= lox && ua < g.BX - lox && ((x >> (16 * k)) & 0xFFFFull) != 0;
+                    pb[j] = ub >= lox && ub < g.BX - lox && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
+                    qa[j] = ua | (v << 10) | (w << 20);
+                    qb[j] = ub | (v << 10) | (w << 20);
                 }
-                const uint64_t ma = __ballot(pa), mb = __ballot(pb);
-                const uint32_t na = (uint32_t)__popcll(ma), n = na + (uint32_t)__popcll(mb);
+                }
+                const uint64_t ma0 = __ballot(pa[0]), mb0 = __ballot(pb[0]);
+                const uint64_t ma1 = __ballot(pa[1]), mb1 = __ballot(pb[1]);
+                const uint32_t o1 = (uint32_t)__popcll(ma0);
+                const uint32_t o2 = o1 + (uint32_t)__popcll(mb0);
+                const uint32_t o3 = o2 + (uint32_t)__popcll(ma1);
+                const uint32_t n = o3 + (uint32_t)__popcll(mb1);
                 if (n) {
                     uint32_t base = 0;
                     if (lane == 0) base = atomicAdd(qc, n);
-                    base = __shfl(base, 0);
-                    if (pa) queue[base + (uint32_t)__popcll(ma & lanes_below)] = qa;
-                    if (pb) queue[base + na + (uint32_t)__popcll(mb & lanes_below)] = qb;
+                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                    if (pa[0]) queue[base + (uint32_t)__popcll(ma0 & lanes_below)] = qa[0];
+                    if (pb[0]) queue[base + o1 + (uint32_t)__popcll(mb0 & lanes_below)] = qb[0];
+                    if (pa[1]) queue[base + o2 + (uint32_t)__popcll(ma1 & lanes_below)] = qa[1];
+                    if (pb[1]) queue[base + o3 + (uint32_t)__popcll(mb1 & lanes_below)] = qb[1];
                 }
             }
         } else {
@@ -455,7 +470,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     if (mask) {
                         uint32_t base = 0;
                         if (lane == 0) base = atomicAdd(qc, (uint32_t)__popcll(mask));
-                        base = __shfl(base, 0);
+                        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
                         if (push[j]) queue[base + (uint32_t)__popcll(mask & lanes_below)] = packed[j];
                     }
                 }
