@@ -269,7 +269,8 @@ __device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, const int32_t
         const int32_t* rc = a.Jp + (int64_t)c * a.Q;
         int64_t acc = 0;
 #pragma unroll
-        for (int m = 0; m < M; ++m) acc += (int64_t)rc[nb[m]] - (int64_t)rq[nb[m]];
+        for (int m = 0; m < M; ++m)   // a value outside [0, Q) bonds with nothing
+            if ((uint32_t)nb[m] < (uint32_t)a.Q) acc += (int64_t)rc[nb[m]] - (int64_t)rq[nb[m]];
         d = acc;
     } else {
         int cq = 0, cc = 0;
@@ -293,6 +294,8 @@ __device__ __forceinline__ int32_t nf_uniform_candidate(const NfLat& a, int32_t 
 
 // Weight of site j; in the neighbour mode `only` < 0 counts every slot,
 // otherwise slot `only` alone (its candidate returned in cand, -1 if empty).
+// Values outside [0, Q) (a wrapped buffer may hold them) are inert, as in
+// the sweep: such a site never moves and such a neighbour is never proposed.
 template <int NBR, typename Spin, bool kUniform, bool kPair>
 __device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t* B, uint32_t j, int only,
                                    int32_t& cand) {
@@ -300,13 +303,15 @@ __device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t*
     const int32_t q = nf_gather<NBR>(s, a, j, nb);
     uint64_t w = 0;
     cand = -1;
+    if ((uint32_t)q >= (uint32_t)a.Q) return 0;
     if constexpr (kUniform) {
         for (int k = 0; k < a.S; ++k) w += nf_slot_weight<NBR, kPair>(a, B, q, nf_uniform_candidate(a, q, k), nb);
     } else {
 #pragma unroll
         for (int k = 0; k < nf_M<NBR>(); ++k) {
-            if (k == only) cand = nb[k] == q ? -1 : nb[k];
-            if ((only < 0 || k == only) && nb[k] != q) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+            const bool valid = nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
+            if (k == only) cand = valid ? nb[k] : -1;
+            if ((only < 0 || k == only) && valid) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
         }
     }
     return w;
@@ -614,7 +619,13 @@ hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT
     const uint64_t call_tick = buf->tick + 1;
     for (int32_t b = 0; b < count; ++b) {
         hmc_lattice* L = lats[b];
-        HMC_HIP(hipStreamSynchronize(L->stream));
+        // the batch runs on the first lattice's stream: wait for work still
+        // queued on another lattice's stream (an idle stream costs a query)
+        if (L->stream != L0->stream) {
+            const hipError_t q = hipStreamQuery(L->stream);
+            if (q == hipErrorNotReady) HMC_HIP(hipStreamSynchronize(L->stream));
+            else if (q != hipSuccess) return hip_fail(q, "hipStreamQuery");
+        }
         NfLat& a = args[(size_t)b];
         uint32_t bits;
         std::memcpy(&bits, &kT[b], sizeof bits);
@@ -679,8 +690,6 @@ hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT
         L->nf_t_last = clocks[(size_t)b].t_last;
         L->nf_events = clocks[(size_t)b].n_events;
         L->nf_t_now = args[(size_t)b].t_end;
-        HMC_TRY(settle_borrowed(L));
-        if (L != L0) HMC_HIP(hipStreamSynchronize(L->stream));
     }
     return HMC_OK;
 }

@@ -250,6 +250,22 @@ def nfold_ensemble_128(count=1024, seed=6006, n_mcs=20):
     return out
 
 
+def nfold_strip_128(count=1024, n_mcs=100):
+    """The regime the rejection-free method is for: `count` VN4 128^2
+    lattices (int16), each a flat strip of grain 1 (rows 32..95) in grain 0
+    with a bulk energy 0.3 J higher, at kT 0.3.  The flat boundaries move
+    only through thermally activated kinks (a few events per MC step per
+    lattice) while a sweep still tries every boundary site each step.  Event
+    seed 7000+j."""
+    B = quantise(np.array([0.0, 0.3]))
+    out: List[Workload] = []
+    for j in range(count):
+        w = Workload(f"nfold_strip_128[{j}]", (128, 128), VN4, I16, 2, 0.3, n_mcs, 0, 7000 + j, B)
+        w.extra["spins"] = flat_strip(128, 128)
+        out.append(w)
+    return out
+
+
 def ensemble_moore8(count=64, seed=4004, n_mcs=1000):
     rng = np.random.Generator(np.random.PCG64(seed))
     sides = rng.choice(np.array([128, 256, 512, 1024]), size=count)

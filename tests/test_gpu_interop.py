@@ -134,3 +134,30 @@ def test_mlp_infer_on_device_and_side_stream():
             hmc.hmc_mlp_infer(M, 0, yd.data_ptr(), 10, None)
     finally:
         hmc.hmc_mlp_free(M)
+
+
+@pytest.mark.parametrize("pair", [False, True])
+def test_nfold_on_wrapped_tensor_keeps_out_of_range_values(pair):
+    """The n-fold way on a caller's buffer that holds values outside [0, Q):
+    those sites never move and are never proposed (as in the sweep), and
+    with pair bond energies they bond with nothing."""
+    dims, Q = (32, 32), 4
+    say(f"[gpu] nfold on a wrapped tensor with out-of-range values, pair={pair}")
+    rng = np.random.default_rng(2)
+    s = rng.integers(0, Q, size=(32, 32)).astype(np.int32)
+    s[10:14, 6:20] = -1
+    s[0, 0] = 99
+    t = _tensor_from(s, torch.int32)
+    stream = torch.cuda.current_stream().cuda_stream
+    with hmc.Lattice(dims, hmc.HMC_VN4, Q, spin=hmc.HMC_I32, stream=stream, dev_ptr=t.data_ptr()) as lat:
+        lat.set_grain_energy(np.array([0, 3000, -2000, 1000], np.int32))
+        if pair:
+            A = np.triu(rng.integers(20000, 90000, size=(Q, Q)), 1)
+            lat.set_pair_energy((A + A.T).astype(np.int32))
+        lat.nfold(0.8, 3.0, 5)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy()
+        assert np.array_equal(got, lat.spins())
+        assert np.all(got[10:14, 6:20] == -1) and got[0, 0] == 99
+        assert lat.nfold_clock()[2] > 50
+        assert not np.array_equal(got, s)

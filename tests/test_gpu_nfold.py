@@ -241,3 +241,20 @@ def test_nfold_batch_with_many_temperatures():
     finally:
         for lat in lats:
             lat.close()
+
+
+def test_nfold_driven_flat_strip():
+    """A flat strip of a grain with higher bulk energy at low temperature
+    (thermally activated kinks): spins set from the host, parity with the
+    oracle, and the strip shrinks."""
+    s = np.zeros((64, 96), np.int32)
+    s[16:48, :] = 1
+    B = np.array([0, 19661], np.int32)
+    with hmc.Lattice((96, 64), hmc.HMC_VN4, 2) as lat:
+        lat.set_spins(s)
+        lat.set_grain_energy(B)
+        lat.nfold(0.3, 60.0, 17)
+        want, t_last, ne, _ = oracle.nfold(s, hmc.HMC_VN4, (96, 64), B, 0.3, 17, 60.0)
+        assert np.array_equal(lat.spins().astype(np.int32), want)
+        assert lat.nfold_clock() == (60.0, t_last, ne)
+        assert ne > 100 and want.sum() < s.sum()
