@@ -40,7 +40,7 @@ std::vector<Tiling> candidates(const hmc_lattice_desc& d) {
     const std::vector<int> sides3 = {4, 8, 16, 32, 64};
     // MC steps per launch; with four or eight colours also launches of 1, 2
     // or 4 colour passes (negative k), whose halos are thinner
-    std::vector<int> ks = {1, 2, 4, 8};
+    std::vector<int> ks = {1, 2, 3, 4, 5, 6, 8};
     if (C >= 4) ks.insert(ks.end(), {-1, -2, -4});
     auto divides = [&](int s, int L) { return s <= L && L % s == 0; };
     if (d.ndim == 2) {
