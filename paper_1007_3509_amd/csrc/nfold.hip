@@ -317,6 +317,37 @@ __device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t*
     return w;
 }
 
+// Weight of site j in the neighbour mode as if site `at` held spin `val`
+// (at = ~0: as it is); `only` < 0 counts every slot, otherwise slot `only`
+// alone (its candidate returned in cand).  One code path for every lane of
+// a pass, whatever it weighs.
+template <int NBR, typename Spin, bool kPair>
+__device__ uint64_t nf_site_weight_if(const Spin* s, const NfLat& a, const int32_t* B, uint32_t j, uint32_t at,
+                                      int32_t val, int only, int32_t& cand) {
+    constexpr int M = nf_M<NBR>();
+    uint32_t x, y, z;
+    nf_coords(a, j, x, y, z);
+    int32_t nb[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const uint32_t n = nf_neighbour<NBR>(a, x, y, z, k);
+        const int32_t v = (int32_t)s[n];
+        nb[k] = n == at ? val : v;
+    }
+    const int32_t sj = (int32_t)s[j];
+    const int32_t q = j == at ? val : sj;
+    cand = -1;
+    if ((uint32_t)q >= (uint32_t)a.Q) return 0;
+    uint64_t w = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const bool valid = nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
+        if (k == only) cand = valid ? nb[k] : -1;
+        if ((only < 0 || k == only) && valid) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+    }
+    return w;
+}
+
 template <int NBR, typename Spin, bool kUniform, bool kPair>
 __device__ __forceinline__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t* B, uint32_t j) {
     int32_t unused;
@@ -415,6 +446,54 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
             const int pick = wave_pick(w, r);
             ok = pick >= 0 && p * 64u + (uint32_t)pick < a.N;
             site = ok ? p * 64u + (uint32_t)pick : 0u;
+        }
+        // Neighbourhoods of at most six: one pass weighs the chosen site's
+        // slots (lanes 0..M-1), the site and its neighbours before the flip
+        // (lanes M..2M) and, for every slot it might take, after it (lanes
+        // 2M+1 + s(M+1) + a), so no pass has to wait for the flip.
+        constexpr bool kSpec = !kUniform && M <= 6;
+        if constexpr (kSpec) {
+            if (!ok) {
+                state = kNfBroken;
+                break;
+            }
+            constexpr int kB = M, kA = 2 * M + 1;
+            int role_a = -1, role_s = -1;
+            if (lane >= kB && lane < kA) role_a = lane - kB;
+            if (lane >= kA && lane < kA + M * (M + 1)) {
+                role_s = (lane - kA) / (M + 1);
+                role_a = lane - kA - role_s * (M + 1);
+            }
+            const uint32_t jr = role_a >= 1 ? nf_neighbour_of<NBR>(a, site, role_a - 1) : site;
+            const int32_t val = (int32_t)s[nf_neighbour_of<NBR>(a, site, role_s >= 0 ? role_s : 0)];
+            int32_t cand = -1;
+            const uint64_t w = nf_site_weight_if<NBR, Spin, kPair>(s, a, B, jr, role_s >= 0 ? site : ~0u, val,
+                                                                    role_a >= 0 ? -1 : lane, cand);
+            const int pick = wave_pick(lane < M ? w : 0ull, r);
+            const int32_t cnew = (int32_t)lane_value((uint32_t)cand, pick < 0 ? 0 : pick);
+            if (pick < 0 || cnew < 0 || cnew >= a.Q) {   // the tree disagrees with the spins
+                state = kNfBroken;
+                break;
+            }
+            // lanes M..2M take the weight after the chosen flip from its lane
+            const int src = kA + pick * (M + 1) + (role_a >= 0 && role_s < 0 ? role_a : 0);
+            const uint64_t after = __shfl(w, src, 64);
+            if (role_a >= 0 && role_s < 0 && after != w) {
+                const unsigned long long delta = (unsigned long long)(after - w);
+                uint32_t idx = jr;
+#pragma unroll
+                for (int L = 1; L <= kNfMaxLevels; ++L) {
+                    if (L > lv.T) break;
+                    idx >>= 6;
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&tree[lv.off[L] + idx]), delta);
+                }
+                atomicAdd(reinterpret_cast<unsigned long long*>(root), delta);
+            }
+            if (lane == 0) s[site] = (Spin)cnew;
+            __syncthreads();
+            t_last = t_next;
+            ++n;
+            continue;
         }
         // lanes 32..32+M: the site and its M neighbours, whose weights change
         const int aff = lane - 32;
