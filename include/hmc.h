@@ -319,10 +319,14 @@ hmc_status hmc_ensemble_free(hmc_ensemble *E);
  *     a run between calls changes nothing.  A lattice with W = 0 has no event.
  * Each lattice carries its own clock (t_now, t_last, n_events), starting at
  * zero, separate from the MC-step counter of hmc_sweep; snapshots include it.
- * The lattice's spins live in LDS during a call (N * spin size + N/8 bytes
- * must fit the device's LDS, 160 KiB on MI355X: up to about 75 000 int16 or
- * 38 000 int32 sites); per-site fields are not supported (HMC_E_STATE);
- * the UNIFORM mode needs uniform bonds and Q <= 65.  Calls are synchronous. */
+ * Spin values outside [0, Q) (a wrapped buffer may hold them) are inert, as
+ * in the sweep: such a site has weight 0 and such a neighbour is never
+ * proposed and, with a pair table, bonds with nothing.
+ * The lattice's spins live in LDS during a call (N * spin size + N/8 + 4 Q
+ * bytes must fit the device's LDS, 160 KiB on MI355X: up to about 75 000
+ * int16 or 38 000 int32 sites, else HMC_E_RANGE); per-site fields are not
+ * supported (HMC_E_STATE); the UNIFORM mode needs uniform bonds and Q <= 65.
+ * Calls are synchronous. */
 
 /* Advance one lattice by mcs MC steps of continuous time. */
 hmc_status hmc_nfold(hmc_lattice *L, float kT, double mcs, uint64_t seed);
