@@ -345,6 +345,17 @@ hmc_status hmc_nfold_clock(const hmc_lattice *L, double *t_now, double *t_last, 
 /* Set the clock (a restart from saved spins); t_last <= t_now, both finite. */
 hmc_status hmc_nfold_set_clock(hmc_lattice *L, double t_now, double t_last, uint64_t n_events);
 
+/* Self-test of the event loop's waiting-time variate: out[c] = E of event
+ * n0 + c under `seed` (drawn after its two selection words, 32.32 fixed
+ * point), computed on the current device with the event kernel's own code.
+ * The kernel measures a decreasing run in one step when it ends inside the
+ * first `window` words of the event's stream and walks it word by word
+ * otherwise; window 64 is the event loop's, 4, 7 and 16 send more runs down
+ * the word-by-word path.  Every window gives the same values.  out: host,
+ * count entries (count <= 2^26, else HMC_E_RANGE); any other window is
+ * HMC_E_INVAL.  Synchronous. */
+hmc_status hmc_nfold_exponentials(uint64_t seed, uint64_t n0, int64_t count, int32_t window, uint64_t *out);
+
 /* ------------------------------------------------------------ autotuner
  * Time candidate tilings (tile sides x MC steps per launch) of hmc_sweep on
  * a scratch lattice with this descriptor, n_grains Voronoi grains and zero

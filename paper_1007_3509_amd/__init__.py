@@ -89,6 +89,7 @@ _SIGS = [
     ("hmc_nfold_clock", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_uint64)]),
     ("hmc_nfold_set_clock", C.c_int32, [C.c_void_p, C.c_double, C.c_double, C.c_uint64]),
+    ("hmc_nfold_exponentials", C.c_int32, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int32, C.c_void_p]),
     ("hmc_autotune", C.c_int32, [C.POINTER(hmc_lattice_desc), C.c_int32, C.c_float, C.c_int32, C.c_char_p,
                                  C.c_void_p, C.POINTER(C.c_double)]),
     ("hmc_tuning_load", C.c_int32, [C.c_char_p, C.POINTER(C.c_int32)]),
@@ -375,6 +376,12 @@ def hmc_nfold_clock(h):
 
 def hmc_nfold_set_clock(h, t_now, t_last, n_events):
     _check(lib().hmc_nfold_set_clock(h, float(t_now), float(t_last), int(n_events)))
+
+
+def hmc_nfold_exponentials(seed, n0, count, window=64):
+    out = np.zeros(int(count), dtype=np.uint64)
+    _check(lib().hmc_nfold_exponentials(int(seed), int(n0), int(count), int(window), _ptr(out)))
+    return out
 
 
 def hmc_autotune(desc, n_grains, kT, n_mcs, cache_path=None):

@@ -256,6 +256,7 @@ hmc_status settle_borrowed(hmc_lattice* L);
 // n-fold way (nfold.hip): LDS a lattice needs, and a batch run of lattices
 // that share neighbourhood, spin type, trial mode and bond model.
 size_t nfold_lds_bytes(int64_t N, size_t spin_bytes, int32_t Q);
+hmc_status nfold_exponentials(uint64_t seed, uint64_t n0, int64_t count, int32_t window, uint64_t* out);
 hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT, double mcs, const uint64_t* seed);
 
 }  // namespace hmc

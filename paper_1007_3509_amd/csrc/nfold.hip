@@ -151,13 +151,16 @@ __device__ __forceinline__ int wave_pick(uint64_t v, uint64_t& r) {
     return c;
 }
 
-// The words of one event's Philox stream.  Lanes 0..3 compute blocks 0..3
-// side by side (16 words: almost every event needs fewer); words beyond
-// them come from one further block at a time.
+// The words of one event's Philox stream.  Lane l computes block l / 4 and
+// keeps its word l % 4, so the wave holds words 0..63 at once; words beyond
+// them come from one further block at a time.  `desc` has bit k set when
+// word k+1 < word k (k < 63), which lets a whole decreasing run be measured
+// with one bit scan.
 struct NfWords {
     uint32_t n_lo, n_hi, k0, k1;
-    uint32_t o0, o1, o2, o3;     // lane l: block l & 3
-    uint32_t e0, e1, e2, e3;     // the current block beyond the first four
+    uint32_t wl;                 // lane l: word l
+    uint64_t desc;
+    uint32_t e0, e1, e2, e3;     // the current block beyond the first sixteen
     int w;                       // next word (uniform)
     __device__ void start(uint64_t n, uint32_t key0, uint32_t key1, int lane) {
         n_lo = (uint32_t)n;
@@ -165,18 +168,19 @@ struct NfWords {
         k0 = key0;
         k1 = key1;
         uint32_t o[4];
-        philox4x32_10(n_lo, n_hi, kNfTag, (uint32_t)(lane & 3), k0, k1, o);
-        o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
+        philox4x32_10(n_lo, n_hi, kNfTag, (uint32_t)(lane >> 2), k0, k1, o);
+        const int c = lane & 3;
+        wl = c == 0 ? o[0] : c == 1 ? o[1] : c == 2 ? o[2] : o[3];
+        const uint32_t up = (uint32_t)__shfl_down((int)wl, 1, 64);   // word l+1
+        desc = (uint64_t)__ballot(lane < 63 && up < wl);
         e0 = e1 = e2 = e3 = 0u;
         w = 0;
     }
+    __device__ uint32_t word(int idx) const { return lane_value(wl, idx); }   // idx < 64, uniform
     __device__ uint32_t next() {
         const int idx = w++;
+        if (idx < 64) return word(idx);
         const int c = idx & 3;
-        if (idx < 16) {
-            const uint32_t v = c == 0 ? o0 : c == 1 ? o1 : c == 2 ? o2 : o3;
-            return lane_value(v, idx >> 2);
-        }
         if (c == 0) {
             uint32_t o[4];
             philox4x32_10(n_lo, n_hi, kNfTag, (uint32_t)(idx >> 2), k0, k1, o);
@@ -187,21 +191,38 @@ struct NfWords {
 };
 
 // von Neumann (1951): a trial takes u0 and the length n of the strictly
-// decreasing run it starts; odd n accepts E = K + u0 / 2^32, even n adds one
-// to K.  Runs are cut at 64 words and K at 64.
+// decreasing run it starts (the word that ends the run is used up); odd n
+// accepts E = K + u0 / 2^32, even n adds one to K.  Runs are cut at 64 words
+// and K at 64.  A run that ends inside the first kWin words is measured from
+// `desc` (c further words continue it, the next one breaks it); any other
+// run is walked word by word.  kWin is 64 in the event loop; the self-test
+// entry point also builds smaller windows so that both paths are exercised.
+template <int kWin = 64>
 __device__ __forceinline__ uint64_t nf_exponential(NfWords& w) {
+    static_assert(kWin >= 2 && kWin <= 64, "the window lies in the wave's 64 words");
+    const uint64_t desc = kWin == 64 ? w.desc : w.desc & ((1ull << (kWin - 1)) - 1);   // bits < kWin - 1
     uint64_t K = 0;
     for (;;) {
-        const uint32_t u0 = w.next();
-        uint32_t prev = u0;
-        int n = 1;
-        while (n < 64) {
-            const uint32_t v = w.next();
-            if (v < prev) {
-                prev = v;
-                ++n;
-            } else {
-                break;
+        uint32_t u0;
+        int n;
+        const int p = w.w;
+        const int c = p <= kWin - 2 ? (int)__builtin_ctzll(~(desc >> p)) : 64;   // bit kWin-1 of desc is 0
+        if (p + c <= kWin - 2) {
+            u0 = w.word(p);
+            n = c + 1;            // <= 61: p >= 2
+            w.w = p + c + 2;
+        } else {
+            u0 = w.next();
+            uint32_t prev = u0;
+            n = 1;
+            while (n < 64) {
+                const uint32_t v = w.next();
+                if (v < prev) {
+                    prev = v;
+                    ++n;
+                } else {
+                    break;
+                }
             }
         }
         if (n & 1) return (K << 32) | (uint64_t)u0;
@@ -257,6 +278,14 @@ __device__ __forceinline__ int32_t nf_gather(const Spin* s, const NfLat& a, uint
     return (int32_t)s[j];
 }
 
+// The lattice descriptors are read from device memory, so the compiler cannot
+// tell that their pointers are global and would emit flat loads, which also
+// hold up every later LDS wait; this cast makes them global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* nf_global(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Weight of moving a site with spin q and neighbour spins nb to spin c != q;
 // B is the LDS copy of the grain energies.
 template <int NBR, bool kPair>
@@ -265,8 +294,8 @@ __device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, const int32_t
     constexpr int M = nf_M<NBR>();
     int64_t d;
     if constexpr (kPair) {
-        const int32_t* rq = a.Jp + (int64_t)q * a.Q;
-        const int32_t* rc = a.Jp + (int64_t)c * a.Q;
+        const auto* rq = nf_global(a.Jp) + (int64_t)q * a.Q;
+        const auto* rc = nf_global(a.Jp) + (int64_t)c * a.Q;
         int64_t acc = 0;
 #pragma unroll
         for (int m = 0; m < M; ++m)   // a value outside [0, Q) bonds with nothing
@@ -283,7 +312,7 @@ __device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, const int32_t
     }
     d += (int64_t)B[c] - (int64_t)B[q];
     if (d <= 0) return 1ull << 32;
-    return (uint64_t)a.Tg[d < a.Dmax ? d : a.Dmax];
+    return (uint64_t)nf_global(a.Tg)[d < a.Dmax ? d : a.Dmax];
 }
 
 // Candidate spin of slot k in the symmetric trial mode.
@@ -370,9 +399,9 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
     uint64_t* root = tree + lv.total;
     int32_t* B = reinterpret_cast<int32_t*>(root + 1);
 
-    const Spin* gs = static_cast<const Spin*>(a.spins);
+    const auto* gs = nf_global(static_cast<const Spin*>(a.spins));
     for (uint32_t i = (uint32_t)lane; i < a.N; i += kNfThreads) s[i] = gs[i];
-    for (int32_t q = lane; q < a.Q; q += kNfThreads) B[q] = a.B[q];
+    for (int32_t q = lane; q < a.Q; q += kNfThreads) B[q] = nf_global(a.B)[q];
     __syncthreads();
     // level 1: the weight of every run of 64 sites
     for (uint32_t b = 0; b < lv.n[1]; ++b) {
@@ -420,7 +449,7 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
         wd.start(n, a.k0, a.k1, lane);
         uint64_t u = wd.next();
         u |= (uint64_t)wd.next() << 32;
-        const uint64_t E = nf_exponential(wd);
+        const uint64_t E = nf_exponential<>(wd);
         const double t_next = t_last + (double)(E * (uint64_t)a.S) / (double)W;
         if (!(t_next <= a.t_end)) {
             state = kNfReached;
@@ -665,7 +694,47 @@ hmc_status nf_buffers(int device, size_t n, NfBuffers*& out) {
     return HMC_OK;
 }
 
+// One wave per event stream: the waiting-time variate of events n0, n0+1, ...
+// drawn after the two selection words, with the event loop's own code.
+template <int kWin>
+__global__ __launch_bounds__(kNfThreads) void nfold_exponential_kernel(uint64_t n0, int64_t count, uint32_t k0,
+                                                                       uint32_t k1, uint64_t* __restrict__ out) {
+    const int lane = (int)threadIdx.x;
+    for (int64_t e = blockIdx.x; e < count; e += gridDim.x) {
+        NfWords wd;
+        wd.start(n0 + (uint64_t)e, k0, k1, lane);
+        (void)wd.next();
+        (void)wd.next();
+        const uint64_t E = nf_exponential<kWin>(wd);
+        if (lane == 0) out[e] = E;
+    }
+}
+
 }  // namespace
+
+hmc_status nfold_exponentials(uint64_t seed, uint64_t n0, int64_t count, int32_t window, uint64_t* out) {
+    const void* kfn = window == 64   ? reinterpret_cast<const void*>(&nfold_exponential_kernel<64>)
+                      : window == 16 ? reinterpret_cast<const void*>(&nfold_exponential_kernel<16>)
+                      : window == 7  ? reinterpret_cast<const void*>(&nfold_exponential_kernel<7>)
+                      : window == 4  ? reinterpret_cast<const void*>(&nfold_exponential_kernel<4>)
+                                     : nullptr;
+    if (!kfn) return fail(HMC_E_INVAL, "window must be 4, 7, 16 or 64");
+    if (count < 0 || (count > 0 && !out)) return fail(HMC_E_INVAL, "NULL output or count < 0");
+    if (count > (1ll << 26)) return fail(HMC_E_RANGE, "count must be at most 2^26");
+    if (count == 0) return HMC_OK;
+    void* d = nullptr;
+    const size_t bytes = (size_t)count * sizeof(uint64_t);
+    HMC_TRY(dev_alloc(&d, bytes, "n-fold exponentials"));
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint64_t* dout = static_cast<uint64_t*>(d);
+    void* kargs[] = {&n0, &count, &k0, &k1, &dout};
+    const unsigned grid = (unsigned)std::min<int64_t>(count, 4096);
+    hipError_t e = hipLaunchKernel(kfn, dim3(grid), dim3(kNfThreads), kargs, 0, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d, bytes, hipMemcpyDeviceToHost);
+    dev_free(d, bytes);
+    if (e != hipSuccess) return hip_fail(e, "n-fold exponentials");
+    return HMC_OK;
+}
 
 size_t nfold_lds_bytes(int64_t N, size_t spin_bytes, int32_t Q) { return nf_lds_bytes((uint32_t)N, spin_bytes, Q); }
 

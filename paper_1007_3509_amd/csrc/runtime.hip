@@ -842,6 +842,11 @@ hmc_status hmc_nfold(hmc_lattice* L, float kT, double mcs, uint64_t seed) {
     return hmc_nfold_batch(&L, 1, &kT, mcs, &seed);
 }
 
+hmc_status hmc_nfold_exponentials(uint64_t seed, uint64_t n0, int64_t count, int32_t window, uint64_t* out) {
+    g_error.clear();
+    return nfold_exponentials(seed, n0, count, window, out);
+}
+
 hmc_status hmc_nfold_clock(const hmc_lattice* L, double* t_now, double* t_last, uint64_t* n_events) {
     g_error.clear();
     if (!L || !t_now || !t_last || !n_events) return fail(HMC_E_INVAL, "NULL argument");

@@ -65,3 +65,18 @@ def test_null_handle_rejected(hmc):
     assert ei.value.status == hmc.HMC_E_INVAL
     with pytest.raises(hmc.HmcError):
         hmc.hmc_get_mcs(None)
+
+
+def test_nfold_waiting_time_arguments(hmc):
+    """The waiting-time self-test checks its arguments before anything is
+    allocated or written."""
+    import numpy as np
+    f = hmc.lib().hmc_nfold_exponentials
+    one = np.zeros(1, np.uint64)
+    for window in (0, 3, 5, 63, 65):
+        assert f(1, 0, 1, window, one.ctypes.data) == hmc.HMC_E_INVAL
+    assert f(1, 0, -1, 64, one.ctypes.data) == hmc.HMC_E_INVAL
+    assert f(1, 0, 1, 64, None) == hmc.HMC_E_INVAL
+    assert f(1, 0, (1 << 26) + 1, 64, one.ctypes.data) == hmc.HMC_E_RANGE
+    assert one[0] == 0
+    assert hmc.hmc_nfold_exponentials(1, 0, 0, 64).size == 0

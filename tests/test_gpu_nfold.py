@@ -7,7 +7,9 @@ Cases span every neighbourhood and spin type, ragged lattices (N not a
 multiple of 64), a lattice with two tree levels run over several launches,
 pair bond energies, the symmetric trial mode, runs split between calls,
 batches of unequal lattices, a lattice without events, snapshots, a run
-after red/black sweeps, and the host-side argument checks.
+after red/black sweeps, the host-side argument checks, and the waiting-time
+variates of the event kernel on their own (both paths of the run
+measurement).
 """
 import numpy as np
 import pytest
@@ -187,6 +189,21 @@ def test_nfold_after_red_black_sweeps():
         assert np.array_equal(lat.spins().astype(np.int32), want)
         assert lat.nfold_clock() == (1.0, t_last, ne)
         assert lat.mcs == 7
+
+
+@pytest.mark.parametrize("window", [4, 7, 16, 64])
+def test_nfold_waiting_times_match_oracle(window):
+    """The event kernel's von Neumann variates, bit for bit: window 64 is the
+    event loop's (a decreasing run that ends inside the wave's 64 words is
+    measured in one step), the smaller windows send most runs, or all of
+    them, down the word-by-word path that a long run takes.  The event
+    numbers cross 2^32."""
+    seed, n0, count = 0x9E3779B97F4A7C15, (1 << 32) - 3000, 60000
+    say(f"[gpu] nfold exponentials window={window} n0={n0} count={count}")
+    got = hmc.hmc_nfold_exponentials(seed, n0, count, window)
+    want = oracle.nfold_exponentials(seed, n0, count)
+    assert np.array_equal(got, want)
+    assert len(np.unique(got >> 32)) > 5      # K reaches several integers
 
 
 def test_nfold_argument_checks():
