@@ -315,6 +315,72 @@ __device__ __forceinline__ uint64_t nf_slot_weight(const NfLat& a, const int32_t
     return (uint64_t)nf_global(a.Tg)[d < a.Dmax ? d : a.Dmax];
 }
 
+// Weights of the neighbour-mode slots of one site (spin q, in range; neighbour
+// spins nb), summed over the slots with use[k] set.  Every slot's d and
+// table index are formed without branches (a slot that is not used gets
+// d = 0) and the M table loads are issued together: in a branch per slot
+// each load waited for the one before it.
+template <int NBR, bool kPair>
+__device__ __forceinline__ uint64_t nf_slots_weight(const NfLat& a, const int32_t* B, int32_t q, const int32_t* nb,
+                                                    const bool* use) {
+    constexpr int M = nf_M<NBR>();
+    if constexpr (kPair && M > 8) {   // 26 slots of 26 pair-table loads: one slot at a time
+        uint64_t w = 0;
+        for (int k = 0; k < M; ++k)
+            if (use[k]) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+        return w;
+    }
+    // d fits in 32 bits: setting energies keeps (largest bond) M + 2 max|B|
+    // below 2^31.  Selections are masks, so that no slot becomes a branch.
+    int32_t d[M];
+    const int32_t bq = B[q];
+    if constexpr (kPair) {
+        const auto* rq = nf_global(a.Jp) + (int64_t)q * a.Q;
+        int32_t nbs[M], in[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {   // a value outside [0, Q) bonds with nothing
+            in[m] = -(int32_t)((uint32_t)nb[m] < (uint32_t)a.Q);
+            nbs[m] = nb[m] & in[m];
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int32_t c = use[k] ? nb[k] : q;
+            const auto* rc = nf_global(a.Jp) + (int64_t)c * a.Q;
+            int32_t acc = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc += (rc[nbs[m]] - rq[nbs[m]]) & in[m];
+            d[k] = (acc + B[c] - bq) & -(int32_t)use[k];
+        }
+    } else {
+        // every grain energy read at an index valid for any slot (an unused
+        // slot's value is masked off), so that no read waits for a branch
+        int32_t bn[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) bn[m] = B[(uint32_t)nb[m] < (uint32_t)a.Q ? nb[m] : q];
+        int cq = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) cq += nb[m] == q;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            int cc = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) cc += nb[m] == nb[k];
+            // unlike bonds after minus before; an unused slot gets d = 0
+            d[k] = (a.J_fx * (cq - cc) + bn[k] - bq) & -(int32_t)use[k];
+        }
+    }
+    uint32_t t[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) t[k] = nf_global(a.Tg)[min(max(d[k], 0), a.Dmax)];   // d <= 0 reads T[0], unused
+    uint64_t w = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const uint64_t wk = d[k] <= 0 ? (1ull << 32) : (uint64_t)t[k];
+        w += wk & (0ull - (uint64_t)use[k]);
+    }
+    return w;
+}
+
 // Candidate spin of slot k in the symmetric trial mode.
 __device__ __forceinline__ int32_t nf_uniform_candidate(const NfLat& a, int32_t q, int k) {
     const int32_t c = q + 1 + k;
@@ -332,16 +398,21 @@ __device__ uint64_t nf_site_weight(const Spin* s, const NfLat& a, const int32_t*
     const int32_t q = nf_gather<NBR>(s, a, j, nb);
     uint64_t w = 0;
     cand = -1;
-    if ((uint32_t)q >= (uint32_t)a.Q) return 0;
+    const bool q_ok = (uint32_t)q < (uint32_t)a.Q;
     if constexpr (kUniform) {
+        if (!q_ok) return 0;
         for (int k = 0; k < a.S; ++k) w += nf_slot_weight<NBR, kPair>(a, B, q, nf_uniform_candidate(a, q, k), nb);
     } else {
+        // no early exit for a site outside [0, Q): its slots are simply unused,
+        // so the spin reads never wait for a branch on q
+        bool use[nf_M<NBR>()];
 #pragma unroll
         for (int k = 0; k < nf_M<NBR>(); ++k) {
-            const bool valid = nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
+            const bool valid = q_ok && nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
             if (k == only) cand = valid ? nb[k] : -1;
-            if ((only < 0 || k == only) && valid) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+            use[k] = (only < 0 || k == only) && valid;
         }
+        w = nf_slots_weight<NBR, kPair>(a, B, q_ok ? q : 0, nb, use);
     }
     return w;
 }
@@ -366,15 +437,15 @@ __device__ uint64_t nf_site_weight_if(const Spin* s, const NfLat& a, const int32
     const int32_t sj = (int32_t)s[j];
     const int32_t q = j == at ? val : sj;
     cand = -1;
-    if ((uint32_t)q >= (uint32_t)a.Q) return 0;
-    uint64_t w = 0;
+    const bool q_ok = (uint32_t)q < (uint32_t)a.Q;
+    bool use[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        const bool valid = nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
+        const bool valid = q_ok && nb[k] != q && (uint32_t)nb[k] < (uint32_t)a.Q;
         if (k == only) cand = valid ? nb[k] : -1;
-        if ((only < 0 || k == only) && valid) w += nf_slot_weight<NBR, kPair>(a, B, q, nb[k], nb);
+        use[k] = (only < 0 || k == only) && valid;
     }
-    return w;
+    return nf_slots_weight<NBR, kPair>(a, B, q_ok ? q : 0, nb, use);
 }
 
 template <int NBR, typename Spin, bool kUniform, bool kPair>
