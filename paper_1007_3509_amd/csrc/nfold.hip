@@ -507,11 +507,15 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
     }
     __syncthreads();
 
+    // Neighbourhoods of at most six take the speculative path below, which
+    // keeps W in a register (the root in LDS is then only the initial sum).
+    constexpr bool kSpec = !kUniform && M <= 6;
+    uint64_t W_reg = *root;
     double t_last = clk->t_last;
     uint64_t n = clk->n_events;
     int32_t state = kNfRunning;
     for (int64_t done = 0; done < max_events; ++done) {
-        const uint64_t W = *root;
+        const uint64_t W = kSpec ? W_reg : *root;
         if (W == 0ull) {
             state = kNfNoEvent;
             break;
@@ -551,7 +555,6 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
         // slots (lanes 0..M-1), the site and its neighbours before the flip
         // (lanes M..2M) and, for every slot it might take, after it (lanes
         // 2M+1 + s(M+1) + a), so no pass has to wait for the flip.
-        constexpr bool kSpec = !kUniform && M <= 6;
         if constexpr (kSpec) {
             if (!ok) {
                 state = kNfBroken;
@@ -578,19 +581,25 @@ __global__ __launch_bounds__(kNfThreads) void nfold_kernel(const NfLat* __restri
             // lanes M..2M take the weight after the chosen flip from its lane
             const int src = kA + pick * (M + 1) + (role_a >= 0 && role_s < 0 ? role_a : 0);
             const uint64_t after = __shfl(w, src, 64);
-            if (role_a >= 0 && role_s < 0 && after != w) {
-                const unsigned long long delta = (unsigned long long)(after - w);
+            const bool upd = role_a >= 0 && role_s < 0;
+            const uint64_t delta = upd ? after - w : 0ull;
+            if (upd && delta != 0ull) {
                 uint32_t idx = jr;
 #pragma unroll
                 for (int L = 1; L <= kNfMaxLevels; ++L) {
                     if (L > lv.T) break;
                     idx >>= 6;
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&tree[lv.off[L] + idx]), delta);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&tree[lv.off[L] + idx]), (unsigned long long)delta);
                 }
-                atomicAdd(reinterpret_cast<unsigned long long*>(root), delta);
             }
+            // the new total from the M+1 site lanes
+#pragma unroll
+            for (int i = 0; i <= M; ++i) W_reg += lane_value64(delta, kB + i);
             if (lane == 0) s[site] = (Spin)cnew;
-            __syncthreads();
+            // One wave per workgroup executes its LDS operations in order, so
+            // the next event's reads see these writes without waiting for them
+            // here; the fence keeps the compiler from moving accesses across.
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             t_last = t_next;
             ++n;
             continue;
