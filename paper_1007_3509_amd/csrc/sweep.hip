@@ -321,12 +321,18 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             if constexpr (kPair) {
                 // dE = sum_k (Jp[q'][s_k] - Jp[q][s_k]) + B[q'] - B[q]; a
                 // neighbour value outside [0, Q) bonds with nothing
+                // (every load at an index valid for any neighbour and masked
+                // after, so the 2M loads issue together instead of each pair
+                // waiting in a branch of its own)
                 const int32_t* Jq = a.Jp + (size_t)q * (uint32_t)a.Q;
                 const int32_t* Jn = a.Jp + (size_t)qn * (uint32_t)a.Q;
                 int32_t d = Bq[qn] - bq;
 #pragma unroll
-                for (int k = 0; k < M; ++k)
-                    if ((uint32_t)nb[k] < (uint32_t)a.Q) d += Jn[nb[k]] - Jq[nb[k]];
+                for (int k = 0; k < M; ++k) {
+                    const int32_t in = -(int32_t)((uint32_t)nb[k] < (uint32_t)a.Q);
+                    const int32_t sk = nb[k] & in;
+                    d += (Jn[sk] - Jq[sk]) & in;
+                }
                 if (d <= 0 || r.r1 < a.Tg[min(d, a.Dmax)]) box[idx] = (Spin)qn;
                 return;
             }
