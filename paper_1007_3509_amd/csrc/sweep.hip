@@ -301,8 +301,11 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
 #pragma unroll
             for (int k = 0; k < M; ++k) nb[k] = (int32_t)box[idx + off[k]];
             const uint32_t site = gxs[u] + a.Lx * (gys[v] + a.Ly * gzs[w]);
-            if ((uint32_t)q >= (uint32_t)a.Q) return;
-            const int32_t bq = Bq[q];
+            // A spin outside [0, Q) never moves; it is tested with the
+            // proposal below rather than by returning here, which would make
+            // the neighbour and coordinate reads wait for q.
+            const bool q_ok = (uint32_t)q < (uint32_t)a.Q;
+            const int32_t bq = Bq[q_ok ? q : 0];
             const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
             int32_t qn;
             int32_t e_new = 0;   // field mode: the swept site's new field
@@ -317,7 +320,7 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                 qn = q + 1 + (int32_t)__umulhi(r.r0, (uint32_t)(a.Q - 1));
                 if (qn >= a.Q) qn -= a.Q;
             }
-            if (qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
+            if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
             if constexpr (kPair) {
                 // dE = sum_k (Jp[q'][s_k] - Jp[q][s_k]) + B[q'] - B[q]; a
                 // neighbour value outside [0, Q) bonds with nothing
