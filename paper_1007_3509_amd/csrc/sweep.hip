@@ -591,10 +591,13 @@ const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair, b
         return grains_in_lds ? reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, true, false>)
                              : reinterpret_cast<const void*>(&ensemble_kernel<NBR, int32_t, false, false>);
     }
-    if (field)   // per-site bulk field; grain energies read from global memory
-        return spin == HMC_I16
-                   ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, false, true>)
-                   : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, false, true>);
+    if (field) {   // per-site bulk field
+        if (spin == HMC_I16)
+            return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, true, kSwar, false, true>)
+                                 : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, false, true>);
+        return grains_in_lds ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, true, false, false, true>)
+                             : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, false, true>);
+    }
     if (pair)   // bond energies from the pair table; grain energies read from global memory
         return spin == HMC_I16 ? reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int16_t, false, kSwar, true>)
                                : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, true>);
@@ -658,7 +661,8 @@ Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tili
     o.bytes = o.grain_off;
     o.grains_in_lds = false;
     const size_t with_grains = o.grain_off + (size_t)maxQ * 4;
-    if (!field && maxQ <= kLdsGrainLimit && (int64_t)with_grains <= lds_limit_bytes()) {
+    const size_t field_bytes = field ? 16 + elems * 4 : 0;   // the field box after the grains, aligned
+    if (maxQ <= kLdsGrainLimit && (int64_t)(with_grains + field_bytes) <= lds_limit_bytes()) {
         o.grains_in_lds = true;
         o.bytes = with_grains;
     }
