@@ -45,7 +45,7 @@ namespace {
 
 constexpr int kNfThreads = 64;                 // one wave per lattice
 constexpr uint32_t kNfTag = 0x4E464F57u;
-constexpr int kNfMaxLevels = 4;                // 64^4 sites: beyond any LDS-resident lattice
+constexpr int kNfMaxLevels = 3;                // 64^3 sites: beyond any LDS-resident lattice
 constexpr int64_t kNfEventsPerLaunch = 1 << 15;
 
 enum : int32_t { kNfRunning = 0, kNfReached = 1, kNfNoEvent = 2, kNfBroken = 3 };
@@ -202,6 +202,29 @@ __device__ __forceinline__ uint64_t nf_exponential(NfWords& w) {
     static_assert(kWin >= 2 && kWin <= 64, "the window lies in the wave's 64 words");
     const uint64_t desc = kWin == 64 ? w.desc : w.desc & ((1ull << (kWin - 1)) - 1);   // bits < kWin - 1
     uint64_t K = 0;
+    // The first four trials as selects, without branches; an event needs
+    // more, or meets a run that leaves the window, about once in fifty, and
+    // the loop below then resumes where they stopped.
+    {
+        int p = w.w, pa = 0, ka = 0;
+        bool done = false, stop = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = p <= kWin - 2 ? (int)__builtin_ctzll(~(desc >> p)) : 64;
+            const bool go = !done && !stop;
+            const bool inw = p + c <= kWin - 2;
+            const bool acc = go && inw && !(c & 1);
+            const bool rej = go && inw && (c & 1);
+            stop = stop || (go && !inw);
+            pa = acc ? p : pa;
+            ka = acc ? (int)K : ka;
+            done = done || acc;
+            K += rej ? 1u : 0u;
+            p = (acc || rej) ? p + c + 2 : p;
+        }
+        w.w = p;
+        if (done) return ((uint64_t)ka << 32) | (uint64_t)w.word(pa);
+    }
     for (;;) {
         uint32_t u0;
         int n;
@@ -819,6 +842,9 @@ hmc_status nfold_exponentials(uint64_t seed, uint64_t n0, int64_t count, int32_t
 size_t nfold_lds_bytes(int64_t N, size_t spin_bytes, int32_t Q) { return nf_lds_bytes((uint32_t)N, spin_bytes, Q); }
 
 hmc_status launch_nfold(hmc_lattice* const* lats, int32_t count, const float* kT, double mcs, const uint64_t* seed) {
+    for (int32_t b = 0; b < count; ++b)   // the weight tree has at most kNfMaxLevels levels of 64-way sums
+        if (lats[b]->N > (1ll << (6 * kNfMaxLevels)))
+            return fail(HMC_E_RANGE, "n-fold way: at most 64^3 sites per lattice");
     hmc_lattice* L0 = lats[0];
     const bool uniform = L0->desc.proposal == HMC_PROP_UNIFORM;
     size_t lds = 0;
