@@ -24,12 +24,16 @@
 // MI355X layout.  One workgroup of one wave per lattice.  The lattice's
 // spins and a 64-ary tree of weight sums sit in LDS (level 1 holds the sum
 // of each run of 64 sites, every level above the sum of 64 entries of the
-// one below, the root the total), so an event is a descent of at most four
+// one below, the root the total), so an event is a descent of at most three
 // levels, each a 64-lane load and a wave-wide 64-bit prefix scan, followed by
 // the weights of the site and its M neighbours recomputed before and after
 // the flip and their differences added up the tree with LDS atomics.  Site
 // weights are not stored: each lane recomputes the weight of its site from
-// the spins in LDS when a descent reaches its run of 64.  Batches put many
+// the spins in LDS when a descent reaches its run of 64.  Each event is a
+// dependent chain in one wave, so the code avoids anything that lengthens
+// it: the 64 random words are generated side by side, a site's table loads
+// are issued together (no branch per slot), and an event's tree updates
+// overlap the next event instead of ending in a barrier.  Batches put many
 // lattices in one launch, one wave each, which is what fills the chip.
 #include <algorithm>
 #include <cmath>
