@@ -66,13 +66,13 @@ def parse():
     return ap.parse_args()
 
 
-def measured_profile(workload, tiling):
-    """Per-launch figures of the sweep kernel from the committed rocprofv3
-    summary (scaled HBM bytes, VALU wave instructions), or {} when the kernel
-    source or the tiling changed since they were taken."""
+def measured_profile(workload, tiling, kernel="sweep_tile_kernel"):
+    """Per-launch figures of the sweep (or ensemble) kernel from the committed
+    rocprofv3 summary (scaled HBM bytes, VALU wave instructions), or {} when
+    the kernel source or the tiling changed since they were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"sweep_tile_kernel_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "sweep.hip")
     if not os.path.exists(path):
         return {}
@@ -306,7 +306,8 @@ def _line(metric, value, args, ms, config, **extra):
 def bench_ensemble(args, hmc):
     """64 Moore-8 lattices of uneven size, temperature and seed: one ensemble
     call (persistent kernel, HIP-graph replay) against the same lattices swept
-    one after another with hmc_sweep."""
+    one after another with hmc_sweep; the ensemble kernel against the HBM
+    roofline; the oracle on the smallest members as the CPU baseline."""
     members = synth.ensemble_moore8()
     n_mcs = args.mcs or members[0].n_mcs
     lats = []
@@ -315,6 +316,7 @@ def bench_ensemble(args, hmc):
         lat.set_grain_energy(w.B)
         hmc.hmc_snapshot(lat.h)
         lats.append(lat)
+    starts = [lat.spins().astype(np.int32) for lat in lats]
     kT = np.array([w.kT for w in members], np.float32)
     seeds = np.array([w.sweep_seed for w in members], np.uint64)
     E = hmc.hmc_ensemble_create(lats)
@@ -322,44 +324,96 @@ def bench_ensemble(args, hmc):
     total_sites = sum(w.n_sites for w in members)
 
     def restore():
+        # every member's initial state, restored outside the timed region
         for lat in lats:
             hmc.hmc_restore(lat.h)
+        for lat in lats:
+            lat.synchronize()
 
     def ens_step():
         restore()
+        t0 = time.perf_counter()
         hmc.hmc_ensemble_sweep(E, kT, seeds, n_mcs)
         hmc.hmc_ensemble_synchronize(E)
+        return time.perf_counter() - t0
 
     def single_step():
         restore()
+        t0 = time.perf_counter()
         for lat, w in zip(lats, members):
             lat.sweep(w.kT, n_mcs, w.sweep_seed)
         for lat in lats:
             lat.synchronize()
+        return time.perf_counter() - t0
 
     res = {}
     for name, fn in (("ensemble", ens_step), ("one_by_one", single_step)):
         for _ in range(args.warmup):
             fn()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        res[name] = (time.perf_counter() - t0) / args.steps
-    # the ensemble's result equals the one-by-one result
+        res[name] = sum(fn() for _ in range(args.steps)) / args.steps
+    # kernel time: HIP events around the graph replay on the ensemble's stream
+    hmc.hmc_ensemble_profile(E, True)
+    hmc.hmc_ensemble_profile_read(E)
     ens_step()
-    a = [lat.spins() for lat in lats]
+    kernel_ms, launches, su_prof = hmc.hmc_ensemble_profile_read(E)
+    hmc.hmc_ensemble_profile(E, False)
+    finals = [lat.spins().astype(np.int32) for lat in lats]
+    # the ensemble's result equals the one-by-one result
     single_step()
-    same = all(np.array_equal(x, lat.spins()) for x, lat in zip(a, lats))
+    same = all(np.array_equal(x, lat.spins()) for x, lat in zip(finals, lats))
     hmc.hmc_ensemble_free(E)
     for lat in lats:
         lat.close()
     su = total_sites * n_mcs
+    C = {hmc.HMC_VN4: 2, hmc.HMC_MOORE8: 4, hmc.HMC_VN6: 2, hmc.HMC_MOORE26: 8}[members[0].nbr]
+    bpsu = (C + 1) * 2   # int16: one pass reads every spin and writes the 1/C it updates
+    launch_s = kernel_ms / 1e3 / max(launches, 1)
+    su_launch = su_prof / max(launches, 1)
+    achieved = su_launch * bpsu / launch_s / 1e9
+    prof = measured_profile("ensemble_moore8", tuple(tiling), kernel="ensemble_kernel")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBPS, "traffic": prof.get("traffic_bytes_per_launch"),
+                "traffic_note": "scaled FETCH_SIZE+WRITE_SIZE bytes per launch from profiles/ (null if the kernel "
+                                "changed)",
+                "kernel": "ensemble_kernel", "avg_launch_us": launch_s * 1e6,
+                "launch_timing": "HIP events around the graph replay on the ensemble's stream (kernels and the gaps "
+                                 "between them), replay of one timed step",
+                "launches": launches, "bytes_per_site_update": bpsu, "site_updates_per_launch": su_launch}
+    if prof.get("valu_wave_instructions_per_launch"):
+        v = prof["valu_wave_instructions_per_launch"]
+        roofline["valu"] = {"wave_instructions_per_launch": v, "per_site_update": v / su_launch,
+                            "issue_frac": v / (VALU_ISSUE_PER_S * launch_s)}
+    extra = {}
+    if not args.no_cpu_baseline:
+        # the oracle on whole members, smallest first, as many as the budget allows
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        order = sorted(range(len(members)), key=lambda i: members[i].n_sites)
+        t0 = time.perf_counter()
+        done, sites, exact = 0, 0, True
+        for i in order:
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+            w = members[i]
+            out = oracle.sweep(starts[i], w.nbr, w.dims, w.B, w.kT, n_mcs, w.sweep_seed, threads=threads)
+            exact = exact and bool(np.array_equal(out, finals[i]))
+            done += 1
+            sites += w.n_sites
+        dt = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": sites * n_mcs / dt, "unit": "site-updates/s", "cores": threads,
+                                 "kind": "oracle",
+                                 "sample": f"the {done} smallest of {len(members)} members, whole {n_mcs}-MCS runs "
+                                           f"({sites * n_mcs:.3g} site updates, {dt:.1f} s)",
+                                 "gpu_bit_exact_on_sample": exact}
     _line("Potts site-updates/s, 64-lattice Moore-8 ensemble, 1 MI355X", su / res["ensemble"], args,
           res["ensemble"] * 1e3,
           {"workload": "ensemble_moore8", "lattices": len(members), "sites": total_sites,
            "mcs_per_step": n_mcs, "tiling": list(tiling)},
+          roofline=roofline,
           one_by_one={"value": su / res["one_by_one"], "ms_per_step": res["one_by_one"] * 1e3},
-          speedup_vs_one_by_one=res["one_by_one"] / res["ensemble"], ensemble_equals_one_by_one=same)
+          speedup_vs_one_by_one=res["one_by_one"] / res["ensemble"], ensemble_equals_one_by_one=same,
+          timing_note="each step times the one ensemble call (and the one-by-one sweeps beside it); restoring "
+                      "the members' initial states runs before the timed region", **extra)
 
 
 def nfold_profile():

@@ -281,6 +281,15 @@ hmc_status hmc_ensemble_sweep(hmc_ensemble *E, const float *kT, const uint64_t *
 /* Wait for the ensemble's stream. */
 hmc_status hmc_ensemble_synchronize(hmc_ensemble *E);
 
+/* Kernel timing of ensemble sweeps: while enabled, HIP events are recorded
+ * on the ensemble's stream around each graph replay (outside the graph), so
+ * the time covers the replay's kernels and the gaps between them.
+ * profile_read synchronises, returns the summed time, the kernel launches
+ * and the site updates (sum over members of N * n_mcs) since enabling or the
+ * last read, and resets the sums.  Errors: INVAL (NULL). */
+hmc_status hmc_ensemble_profile(hmc_ensemble *E, int32_t enable);
+hmc_status hmc_ensemble_profile_read(hmc_ensemble *E, double *kernel_ms, int64_t *launches, int64_t *site_updates);
+
 /* Time candidate tilings on the ensemble's own members (their spins and MC
  * counters are restored afterwards), keep the fastest and return it in
  * best_out4 (tx, ty, tz, k).  n_mcs per candidate; kT/seed as in

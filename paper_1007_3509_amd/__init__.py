@@ -84,6 +84,9 @@ _SIGS = [
     ("hmc_ensemble_synchronize", C.c_int32, [C.c_void_p]),
     ("hmc_ensemble_autotune", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     ("hmc_ensemble_free", C.c_int32, [C.c_void_p]),
+    ("hmc_ensemble_profile", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("hmc_ensemble_profile_read", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64)]),
     ("hmc_nfold", C.c_int32, [C.c_void_p, C.c_float, C.c_double, C.c_uint64]),
     ("hmc_nfold_batch", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p]),
     ("hmc_nfold_clock", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -341,6 +344,16 @@ def hmc_ensemble_sweep(E, kT, seed, n_mcs):
 
 def hmc_ensemble_synchronize(E):
     _check(lib().hmc_ensemble_synchronize(E))
+
+
+def hmc_ensemble_profile(E, enable):
+    _check(lib().hmc_ensemble_profile(E, int(bool(enable))))
+
+
+def hmc_ensemble_profile_read(E):
+    ms, n, su = C.c_double(), C.c_int64(), C.c_int64()
+    _check(lib().hmc_ensemble_profile_read(E, C.byref(ms), C.byref(n), C.byref(su)))
+    return ms.value, n.value, su.value
 
 
 def hmc_ensemble_autotune(E, kT, seed, n_mcs):

@@ -234,6 +234,11 @@ struct hmc_ensemble_s {
     uint32_t grid = 0;
     std::map<int32_t, hipGraphExec_t> graphs;   // captured launch sequences by n_mcs
     uint32_t graph_launches = 0;
+    // event pairs around each graph replay while profiling
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
+    int64_t prof_launches = 0, prof_su = 0;
 };
 
 namespace hmc {

@@ -313,7 +313,7 @@ using namespace hmc;
 
 extern "C" {
 
-int32_t hmc_abi_version(void) { return 3; }
+int32_t hmc_abi_version(void) { return 4; }
 
 const char* hmc_last_error(void) { return g_error.c_str(); }
 
@@ -884,10 +884,40 @@ hmc_status hmc_ensemble_synchronize(hmc_ensemble* E) {
     return HMC_OK;
 }
 
+hmc_status hmc_ensemble_profile(hmc_ensemble* E, int32_t enable) {
+    g_error.clear();
+    if (!E) return fail(HMC_E_INVAL, "ensemble is NULL");
+    E->profiling = enable != 0;
+    return HMC_OK;
+}
+
+hmc_status hmc_ensemble_profile_read(hmc_ensemble* E, double* kernel_ms, int64_t* launches, int64_t* site_updates) {
+    g_error.clear();
+    if (!E || !kernel_ms || !launches || !site_updates) return fail(HMC_E_INVAL, "NULL argument");
+    HMC_HIP(hipStreamSynchronize(E->stream));
+    double total = 0.0;
+    for (size_t i = 0; i < E->events_used; ++i) {
+        float ms = 0.0f;
+        HMC_HIP(hipEventElapsedTime(&ms, E->events[i].first, E->events[i].second));
+        total += ms;
+    }
+    *kernel_ms = total;
+    *launches = E->prof_launches;
+    *site_updates = E->prof_su;
+    E->events_used = 0;
+    E->prof_launches = 0;
+    E->prof_su = 0;
+    return HMC_OK;
+}
+
 hmc_status hmc_ensemble_free(hmc_ensemble* E) {
     g_error.clear();
     if (!E) return HMC_OK;
     (void)hipStreamSynchronize(E->stream);
+    for (auto& e : E->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
     dev_free(E->d_tiles, E->tiles_bytes);
     dev_free(E->d_lats, E->lats_bytes);

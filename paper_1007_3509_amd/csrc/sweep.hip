@@ -1049,7 +1049,22 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         E->graph_launches = j;
     }
     const uint32_t launches = (uint32_t)((n_mcs + E->tiling.k - 1) / E->tiling.k);
-    HMC_HIP(hipGraphLaunch(it->second, E->stream));
+    if (E->profiling) {   // events outside the graph, around its replay
+        if (E->events_used == E->events.size()) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            HMC_HIP(hipEventCreate(&e0));
+            HMC_HIP(hipEventCreate(&e1));
+            E->events.emplace_back(e0, e1);
+        }
+        const auto& ev = E->events[E->events_used++];
+        HMC_HIP(hipEventRecord(ev.first, E->stream));
+        HMC_HIP(hipGraphLaunch(it->second, E->stream));
+        HMC_HIP(hipEventRecord(ev.second, E->stream));
+        E->prof_launches += launches;
+        for (const hmc_lattice* L : E->lats) E->prof_su += (int64_t)L->N * n_mcs;
+    } else {
+        HMC_HIP(hipGraphLaunch(it->second, E->stream));
+    }
     HMC_HIP(hipEventRecord(E->ev, E->stream));
     for (hmc_lattice* L : E->lats) {
         HMC_HIP(hipStreamWaitEvent(L->stream, E->ev, 0));

@@ -80,3 +80,9 @@ def test_nfold_waiting_time_arguments(hmc):
     assert f(1, 0, (1 << 26) + 1, 64, one.ctypes.data) == hmc.HMC_E_RANGE
     assert one[0] == 0
     assert hmc.hmc_nfold_exponentials(1, 0, 0, 64).size == 0
+
+
+def test_ensemble_profile_null_arguments(hmc):
+    f, g = hmc.lib().hmc_ensemble_profile, hmc.lib().hmc_ensemble_profile_read
+    assert f(None, 1) == hmc.HMC_E_INVAL
+    assert g(None, None, None, None) == hmc.HMC_E_INVAL

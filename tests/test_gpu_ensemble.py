@@ -85,6 +85,47 @@ def test_ensemble_graph_replay_and_split_calls():
             l.close()
 
 
+def test_ensemble_profile_counts_launches_and_updates():
+    """Events around each graph replay: the launch and site-update counts are
+    exact, the time is positive and below the host's wall time, profiling
+    changes nothing in the result, and a read resets the sums."""
+    import time
+    specs = [((64, 64), 30, 1), ((128, 64), 60, 2)]
+    kT = np.array([0.6, 0.9], np.float32)
+    seeds = np.array([11, 12], np.uint64)
+    a = _members(specs)
+    b = _members(specs)
+    Ea, Eb = hmc.hmc_ensemble_create(a), hmc.hmc_ensemble_create(b)
+    try:
+        hmc.hmc_ensemble_set_tiling(Ea, 32, 32, 0, 3)
+        hmc.hmc_ensemble_set_tiling(Eb, 32, 32, 0, 3)
+        say("[gpu] ensemble profile")
+        hmc.hmc_ensemble_profile(Ea, True)
+        t0 = time.perf_counter()
+        for _ in range(2):
+            hmc.hmc_ensemble_sweep(Ea, kT, seeds, 10)
+        hmc.hmc_ensemble_synchronize(Ea)
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ms, launches, su = hmc.hmc_ensemble_profile_read(Ea)
+        assert launches == 2 * 4                       # ceil(10 / 3) per call
+        assert su == 2 * 10 * (64 * 64 + 128 * 64)
+        assert 0.0 < ms <= wall_ms
+        assert hmc.hmc_ensemble_profile_read(Ea) == (0.0, 0, 0)
+        hmc.hmc_ensemble_profile(Ea, False)
+        hmc.hmc_ensemble_sweep(Ea, kT, seeds, 10)
+        hmc.hmc_ensemble_synchronize(Ea)
+        assert hmc.hmc_ensemble_profile_read(Ea) == (0.0, 0, 0)
+        hmc.hmc_ensemble_sweep(Eb, kT, seeds, 30)
+        hmc.hmc_ensemble_synchronize(Eb)
+        for x, y in zip(a, b):
+            assert np.array_equal(x.spins(), y.spins())
+    finally:
+        hmc.hmc_ensemble_free(Ea)
+        hmc.hmc_ensemble_free(Eb)
+        for l in a + b:
+            l.close()
+
+
 def test_ensemble_vn4_and_vn6_members():
     for nbr, specs in [(hmc.HMC_VN4, [((64, 96), 40, 3), ((128, 64), 70, 4)]),
                        (hmc.HMC_VN6, [((16, 16, 32), 40, 5), ((32, 16, 16), 70, 6)])]:
