@@ -149,7 +149,7 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check, field=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this library runs on one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import paper_1007_3509_amd as hmc
