@@ -793,7 +793,7 @@ std::vector<Tiling> default_tilings(int nbr) {
         return t;
     };
     switch (nbr) {
-    case HMC_VN4: return {T(64, 64, 1, 5), T(64, 64, 1, 4), T(32, 32, 1, 4), T(16, 16, 1, 2)};
+    case HMC_VN4: return {T(64, 64, 1, 6), T(64, 64, 1, 5), T(32, 32, 1, 4), T(16, 16, 1, 2)};
     case HMC_MOORE8: return {T(64, 64, 1, 2), T(32, 32, 1, 2), T(16, 16, 1, 1)};
     case HMC_VN6: return {T(64, 16, 16, 1), T(32, 32, 16, 1), T(32, 16, 16, 1), T(16, 16, 16, 1), T(8, 8, 8, 1)};
     // eight colours: four colour passes per launch keep the halo at four rings
