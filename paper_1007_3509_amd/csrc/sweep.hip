@@ -939,9 +939,30 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         for (int ax = 0; ax < L0->ndim; ++ax) g[ax] = std::gcd(g[ax], L->desc.dims[ax]);
     }
     E->maxQ = maxQ;
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     if (E->tiling.tx == 0 || E->tiling.k == 0) {
+        // A Moore8 ensemble large enough to give every CU several 128x128
+        // tiles takes them with 3 MC steps per launch: the 4-colour halo is a
+        // smaller share of a big tile (64 members, 29 M sites: 251 -> 129 ms
+        // per 1000 steps against 64x64 tiles with 2).  Smaller ensembles, and
+        // single lattices, keep the defaults, which fill the chip.
+        std::vector<Tiling> cands;
+        if (L0->desc.nbr == HMC_MOORE8 && L0->ndim == 2) {
+            Tiling big;
+            big.tx = 128; big.ty = 128; big.tz = 1; big.k = 3;
+            bool divides = true;
+            int64_t n = 0;
+            for (const hmc_lattice* L : E->lats) {
+                divides = divides && L->desc.dims[0] % big.tx == 0 && L->desc.dims[1] % big.ty == 0;
+                n += (int64_t)(L->desc.dims[0] / big.tx) * (L->desc.dims[1] / big.ty);
+            }
+            if (divides && n >= 4 * (int64_t)cus) cands.push_back(big);
+        }
+        for (const Tiling& d : default_tilings(L0->desc.nbr)) cands.push_back(d);
         Tiling t;
-        for (const Tiling& d : default_tilings(L0->desc.nbr)) {
+        for (const Tiling& d : cands) {
             t.tx = largest_even_divisor_at_most(g[0], d.tx);
             t.ty = largest_even_divisor_at_most(g[1], d.ty);
             t.tz = L0->ndim == 3 ? largest_even_divisor_at_most(g[2], d.tz) : 1;
@@ -971,9 +992,6 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         E->lats_bytes = E->lats.size() * sizeof(EnsLat);
         HMC_TRY(dev_alloc(&E->d_lats, E->lats_bytes, "ensemble descriptors"));
     }
-    int cus = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C, false);
     // resident workgroups per CU: two 1024-thread groups fill the wave slots;
     // the LDS of a CU (equal to the per-group limit on gfx950) may allow fewer
