@@ -816,6 +816,35 @@ int lds_limit_bytes() {
     return cached;
 }
 
+int device_cus() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
+// A 2D 16-bit VN4 or Moore8 problem that splits into at least one 128x128
+// tile per CU (n128 tiles; -1 if a side does not divide) takes them, with 6
+// (VN4) or 3 (Moore8) MC steps per launch: the halo of the fused passes is a
+// smaller share of a big tile, and there are enough tiles to fill the chip.
+// Against 64x64 tiles: 2048^2 VN4 2.12 -> 3.40e11 site updates/s, 16384^2
+// 2.41 -> 4.50e11; Moore8 2048^2 1.16 -> 2.18e11.  1024^2 (64 such tiles)
+// keeps 64x64.
+bool large_tiling(int nbr, int ndim, size_t spin_bytes, int64_t n128, Tiling& out) {
+    if (ndim != 2 || spin_bytes != 2 || (nbr != HMC_VN4 && nbr != HMC_MOORE8) || n128 < device_cus()) return false;
+    out.tx = 128;
+    out.ty = 128;
+    out.tz = 1;
+    out.k = nbr == HMC_VN4 ? 6 : 3;
+    return true;
+}
+
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request) {
     const int* dims = L->desc.dims;
     Tiling r = t;
@@ -825,7 +854,14 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
             r = *tuned;
         } else {
             const Tiling req = r;
-            for (const Tiling& d : default_tilings(L->desc.nbr)) {
+            std::vector<Tiling> cands;
+            Tiling big;
+            const int64_t n128 = (dims[0] % 128 == 0 && dims[1] % 128 == 0)
+                                     ? (int64_t)(dims[0] / 128) * (dims[1] / 128) : -1;
+            if (req.tx == 0 && req.ty == 0 && req.k == 0 && large_tiling(L->desc.nbr, L->ndim, L->spin_bytes, n128, big))
+                cands.push_back(big);
+            for (const Tiling& d : default_tilings(L->desc.nbr)) cands.push_back(d);
+            for (const Tiling& d : cands) {
                 r = req;
                 if (r.tx == 0) r.tx = largest_even_divisor_at_most(dims[0], d.tx);
                 if (r.ty == 0) r.ty = largest_even_divisor_at_most(dims[1], d.ty);
@@ -939,27 +975,19 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         for (int ax = 0; ax < L0->ndim; ++ax) g[ax] = std::gcd(g[ax], L->desc.dims[ax]);
     }
     E->maxQ = maxQ;
-    int cus = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const int cus = device_cus();
     if (E->tiling.tx == 0 || E->tiling.k == 0) {
-        // A Moore8 ensemble large enough to give every CU several 128x128
-        // tiles takes them with 3 MC steps per launch: the 4-colour halo is a
-        // smaller share of a big tile (64 members, 29 M sites: 251 -> 129 ms
-        // per 1000 steps against 64x64 tiles with 2).  Smaller ensembles, and
-        // single lattices, keep the defaults, which fill the chip.
+        // the single-lattice rule on the whole ensemble's 128x128 tiles (64
+        // Moore8 members, 29 M sites: 251 -> 130 ms per 1000 steps)
         std::vector<Tiling> cands;
-        if (L0->desc.nbr == HMC_MOORE8 && L0->ndim == 2) {
-            Tiling big;
-            big.tx = 128; big.ty = 128; big.tz = 1; big.k = 3;
-            bool divides = true;
-            int64_t n = 0;
-            for (const hmc_lattice* L : E->lats) {
-                divides = divides && L->desc.dims[0] % big.tx == 0 && L->desc.dims[1] % big.ty == 0;
-                n += (int64_t)(L->desc.dims[0] / big.tx) * (L->desc.dims[1] / big.ty);
-            }
-            if (divides && n >= 4 * (int64_t)cus) cands.push_back(big);
+        bool divides = true;
+        int64_t n128 = 0;
+        for (const hmc_lattice* L : E->lats) {
+            divides = divides && L->desc.dims[0] % 128 == 0 && L->desc.dims[1] % 128 == 0;
+            n128 += (int64_t)(L->desc.dims[0] / 128) * (L->desc.dims[1] / 128);
         }
+        Tiling big;
+        if (large_tiling(L0->desc.nbr, L0->ndim, L0->spin_bytes, divides ? n128 : -1, big)) cands.push_back(big);
         for (const Tiling& d : default_tilings(L0->desc.nbr)) cands.push_back(d);
         Tiling t;
         for (const Tiling& d : cands) {

@@ -248,3 +248,25 @@ def test_grain_energy_placement(Q, spread):
     start, got = gpu_run(dims, hmc.HMC_VN4, Q, B, 0.9, 12, 77, vseed=5)
     want = oracle.sweep(start, hmc.HMC_VN4, dims, B, 0.9, 12, 77, threads=THREADS)
     assert_same(got, want, f"Q={Q} spread={spread}")
+
+
+@pytest.mark.parametrize("nbr,k", [(hmc.HMC_VN4, 6), (hmc.HMC_MOORE8, 3)])
+def test_large_lattice_default_takes_128_tiles(nbr, k):
+    """A 2048^2 int16 lattice splits into one 128x128 tile per CU of an
+    MI355X, so the default takes them; the result equals the oracle's and a
+    64x64 tiling's."""
+    dims, Q, n_mcs = (2048, 2048), 3000, 13
+    B = synth.quantise(0.2 * (0.27 + 0.23 * np.random.default_rng(21).random(Q)))
+    say(f"[gpu] 2048^2 nbr={nbr} default tiling")
+    with hmc.Lattice(dims, nbr, Q, voronoi_seed=21) as a, hmc.Lattice(dims, nbr, Q, voronoi_seed=21) as b:
+        a.set_grain_energy(B)
+        b.set_grain_energy(B)
+        start = a.spins().astype(np.int32)
+        assert tuple(hmc.hmc_get_tiling(a.h)) == (128, 128, 1, k)
+        b.set_tiling(64, 64, 1, 2)
+        a.sweep(0.5, n_mcs, 9)
+        b.sweep(0.5, n_mcs, 9)
+        got = a.spins()
+        assert np.array_equal(got, b.spins())
+        want = oracle.sweep(start, nbr, dims, B, 0.5, n_mcs, 9, threads=THREADS)
+        assert np.array_equal(got.astype(np.int32), want)
