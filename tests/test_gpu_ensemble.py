@@ -185,3 +185,36 @@ def test_autotuners_keep_results():
     hmc.hmc_ensemble_free(E)
     for l in lats:
         l.close()
+
+
+def test_large_ensemble_takes_128_tiles_and_matches_singles():
+    """Sixteen 512^2 Moore8 members give one 128x128 tile per CU of an
+    MI355X, so the ensemble takes them (3 MC steps per launch); every member
+    equals its single run (64x64 tiles) and the oracle."""
+    specs = [((512, 512), 300 + 10 * i, 60 + i) for i in range(16)]
+    kT = np.linspace(0.3, 1.0, 16).astype(np.float32)
+    seeds = np.arange(7000, 7016, dtype=np.uint64)
+    n_mcs = 7
+    say("[gpu] large ensemble 16 x 512^2")
+    a = _members(specs)
+    b = _members(specs)
+    starts = [l.spins().astype(np.int32) for l in a]
+    E = hmc.hmc_ensemble_create(a)
+    try:
+        assert tuple(hmc.hmc_ensemble_get_tiling(E)) == (128, 128, 1, 3)
+        hmc.hmc_ensemble_sweep(E, kT, seeds, n_mcs)
+        hmc.hmc_ensemble_synchronize(E)
+        for i, (x, y) in enumerate(zip(a, b)):
+            y.set_tiling(64, 64, 1, 2)
+            y.sweep(float(kT[i]), n_mcs, int(seeds[i]))
+            assert np.array_equal(x.spins(), y.spins()), i
+        for i in (0, 9, 15):
+            lat = a[i]
+            B = synth.quantise(0.2 * (0.27 + 0.23 * np.random.default_rng(specs[i][2]).random(specs[i][1])))
+            want = oracle.sweep(starts[i], hmc.HMC_MOORE8, specs[i][0], B, float(kT[i]), n_mcs, int(seeds[i]),
+                                threads=THREADS)
+            assert np.array_equal(lat.spins().astype(np.int32), want), i
+    finally:
+        hmc.hmc_ensemble_free(E)
+        for l in a + b:
+            l.close()
