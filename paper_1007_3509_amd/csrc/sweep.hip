@@ -829,20 +829,31 @@ int device_cus() {
     return cached;
 }
 
-// A 2D 16-bit VN4 or Moore8 problem that splits into at least one 128x128
-// tile per CU (n128 tiles; -1 if a side does not divide) takes them, with 6
-// (VN4) or 3 (Moore8) MC steps per launch: the halo of the fused passes is a
-// smaller share of a big tile, and there are enough tiles to fill the chip.
-// Against 64x64 tiles: 2048^2 VN4 2.12 -> 3.40e11 site updates/s, 16384^2
-// 2.41 -> 4.50e11; Moore8 2048^2 1.16 -> 2.18e11.  1024^2 (64 such tiles)
-// keeps 64x64.
-bool large_tiling(int nbr, int ndim, size_t spin_bytes, int64_t n128, Tiling& out) {
-    if (ndim != 2 || spin_bytes != 2 || (nbr != HMC_VN4 && nbr != HMC_MOORE8) || n128 < device_cus()) return false;
-    out.tx = 128;
-    out.ty = 128;
+// A 2D 16-bit VN4 or Moore8 problem with at least two 256x128 tiles per CU
+// (n256: their number, -1 if a side does not divide) takes them, with 4
+// (VN4) or 3 (Moore8) MC steps per launch; else one with at least one
+// 128x128 tile per CU (n128) takes those, with 6 or 3 steps.  The halo of
+// the fused passes is a smaller share of a big tile, and there are enough
+// tiles to fill the chip.  VN4 site updates/s against 64x64 tiles: 2048^2
+// 2.12 -> 3.40e11 (128x128); 4096^2 2.20 -> 4.25e11, 16384^2 2.41 ->
+// 5.30e11 (256x128); Moore8 2048^2 1.16 -> 2.13e11, 8192^2 1.30 -> 3.09e11.
+// 1024^2 (64 tiles of 128x128) keeps 64x64.
+bool large_tiling(int nbr, int ndim, size_t spin_bytes, int64_t n128, int64_t n256, Tiling& out) {
+    if (ndim != 2 || spin_bytes != 2 || (nbr != HMC_VN4 && nbr != HMC_MOORE8)) return false;
     out.tz = 1;
-    out.k = nbr == HMC_VN4 ? 6 : 3;
-    return true;
+    if (n256 >= 2 * (int64_t)device_cus()) {
+        out.tx = 256;
+        out.ty = 128;
+        out.k = nbr == HMC_VN4 ? 4 : 3;
+        return true;
+    }
+    if (n128 >= device_cus()) {
+        out.tx = 128;
+        out.ty = 128;
+        out.k = nbr == HMC_VN4 ? 6 : 3;
+        return true;
+    }
+    return false;
 }
 
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request) {
@@ -858,7 +869,10 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
             Tiling big;
             const int64_t n128 = (dims[0] % 128 == 0 && dims[1] % 128 == 0)
                                      ? (int64_t)(dims[0] / 128) * (dims[1] / 128) : -1;
-            if (req.tx == 0 && req.ty == 0 && req.k == 0 && large_tiling(L->desc.nbr, L->ndim, L->spin_bytes, n128, big))
+            const int64_t n256 = (dims[0] % 256 == 0 && dims[1] % 128 == 0)
+                                     ? (int64_t)(dims[0] / 256) * (dims[1] / 128) : -1;
+            if (req.tx == 0 && req.ty == 0 && req.k == 0 &&
+                large_tiling(L->desc.nbr, L->ndim, L->spin_bytes, n128, n256, big))
                 cands.push_back(big);
             for (const Tiling& d : default_tilings(L->desc.nbr)) cands.push_back(d);
             for (const Tiling& d : cands) {
@@ -980,14 +994,17 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         // the single-lattice rule on the whole ensemble's 128x128 tiles (64
         // Moore8 members, 29 M sites: 251 -> 130 ms per 1000 steps)
         std::vector<Tiling> cands;
-        bool divides = true;
-        int64_t n128 = 0;
+        bool div128 = true, div256 = true;
+        int64_t n128 = 0, n256 = 0;
         for (const hmc_lattice* L : E->lats) {
-            divides = divides && L->desc.dims[0] % 128 == 0 && L->desc.dims[1] % 128 == 0;
+            div128 = div128 && L->desc.dims[0] % 128 == 0 && L->desc.dims[1] % 128 == 0;
+            div256 = div256 && L->desc.dims[0] % 256 == 0 && L->desc.dims[1] % 128 == 0;
             n128 += (int64_t)(L->desc.dims[0] / 128) * (L->desc.dims[1] / 128);
+            n256 += (int64_t)(L->desc.dims[0] / 256) * (L->desc.dims[1] / 128);
         }
         Tiling big;
-        if (large_tiling(L0->desc.nbr, L0->ndim, L0->spin_bytes, divides ? n128 : -1, big)) cands.push_back(big);
+        if (large_tiling(L0->desc.nbr, L0->ndim, L0->spin_bytes, div128 ? n128 : -1, div256 ? n256 : -1, big))
+            cands.push_back(big);
         for (const Tiling& d : default_tilings(L0->desc.nbr)) cands.push_back(d);
         Tiling t;
         for (const Tiling& d : cands) {
