@@ -270,3 +270,25 @@ def test_large_lattice_default_takes_128_tiles(nbr, k):
         assert np.array_equal(got, b.spins())
         want = oracle.sweep(start, nbr, dims, B, 0.5, n_mcs, 9, threads=THREADS)
         assert np.array_equal(got.astype(np.int32), want)
+
+
+@pytest.mark.parametrize("nbr,k", [(hmc.HMC_VN4, 4), (hmc.HMC_MOORE8, 3)])
+def test_larger_lattice_default_takes_256x128_tiles(nbr, k):
+    """A 4096^2 int16 lattice splits into two 256x128 tiles per CU of an
+    MI355X, so the default takes them; the result equals the oracle's and a
+    64x64 tiling's."""
+    dims, Q, n_mcs = (4096, 4096), 8000, 5
+    B = synth.quantise(0.2 * (0.27 + 0.23 * np.random.default_rng(23).random(Q)))
+    say(f"[gpu] 4096^2 nbr={nbr} default tiling")
+    with hmc.Lattice(dims, nbr, Q, voronoi_seed=23) as a, hmc.Lattice(dims, nbr, Q, voronoi_seed=23) as b:
+        a.set_grain_energy(B)
+        b.set_grain_energy(B)
+        start = a.spins().astype(np.int32)
+        assert tuple(hmc.hmc_get_tiling(a.h)) == (256, 128, 1, k)
+        b.set_tiling(64, 64, 1, 2)
+        a.sweep(0.5, n_mcs, 4)
+        b.sweep(0.5, n_mcs, 4)
+        got = a.spins()
+        assert np.array_equal(got, b.spins())
+        want = oracle.sweep(start, nbr, dims, B, 0.5, n_mcs, 4, threads=THREADS)
+        assert np.array_equal(got.astype(np.int32), want)
