@@ -153,6 +153,7 @@ static int64_t nf_delta(const nf_lattice *L, int64_t i, int32_t q_new)
     for (k = 0; k < L->M; ++k) {
         int32_t s = L->spins[L->nb[i * L->M + k]];
         if (L->Jp) {
+            if (s < 0 || s >= L->Q) continue;   /* an inert value bonds with nothing */
             before += L->Jp[(int64_t)q * L->Q + s];
             after += L->Jp[(int64_t)q_new * L->Q + s];
         } else {
@@ -167,9 +168,10 @@ static int64_t nf_delta(const nf_lattice *L, int64_t i, int32_t q_new)
 static int32_t nf_candidate(const nf_lattice *L, int64_t i, int k)
 {
     int32_t q = L->spins[i];
+    if (q < 0 || q >= L->Q) return -1;   /* an inert site never changes */
     if (L->proposal == NF_PROP_NEIGHBOUR) {
         int32_t s = L->spins[L->nb[i * L->M + k]];
-        return s == q ? -1 : s;
+        return (s == q || s < 0 || s >= L->Q) ? -1 : s;   /* an inert value is never proposed */
     }
     return (int32_t)(((int64_t)q + 1 + k) % L->Q);
 }
@@ -234,7 +236,9 @@ int64_t orc_nfold_select(const uint64_t *w, int64_t n, uint64_t r, uint64_t *res
 
 /* Advance the lattice with the n-fold way until t_end (MC steps).
  *
- * spins    : int32[N], x fastest, values in [0, Q); updated in place.
+ * spins    : int32[N], x fastest; a value outside [0, Q) is inert (its site
+ *            never changes, it is never proposed, with a pair table it bonds
+ *            with nothing); updated in place.
  * dims     : (Lx, Ly, Lz), every side >= 3 (Lz = 1 for 2D neighbourhoods).
  * B        : int32[Q] grain energies (2^-16 units); J_fx the bond energy.
  * proposal : 0 neighbour slots, 1 the Q-1 other spin values.
@@ -270,8 +274,6 @@ static int64_t nfold_impl(int32_t *spins, int nbr, int proposal, const int32_t d
     L.B = B;
     L.kT = kT;
     L.spins = spins;
-    for (i = 0; i < L.N; ++i)
-        if (spins[i] < 0 || spins[i] >= Q) return -1;
     L.nb = (int64_t *)malloc((size_t)L.N * L.M * sizeof(int64_t));
     nblocks = (L.N + NF_BLOCK - 1) / NF_BLOCK;
     Wsite = (uint64_t *)malloc((size_t)L.N * sizeof(uint64_t));

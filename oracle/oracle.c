@@ -202,6 +202,13 @@ uint32_t orc_threshold(int64_t d, float kT)
     return (uint32_t)floor(v);
 }
 
+/* T(d) for many d (d <= 0 gives 2^32 - 1: always accepted). */
+void orc_threshold_many(const int64_t *d, int64_t n, float kT, uint32_t *out)
+{
+    int64_t i;
+    for (i = 0; i < n; ++i) out[i] = d[i] > 0 ? orc_threshold(d[i], kT) : 0xFFFFFFFFu;
+}
+
 /* Change of Eq. (7) (read with J*(1-delta), each bond once) when site i
  * goes from its spin q to q_new, in 2^-16 units:
  *   dE = J * (#unlike bonds after - #unlike bonds before) + b(q_new) - b(q)
@@ -241,6 +248,7 @@ int64_t orc_delta_energy_pair(const int32_t *spins, int nbr, const int32_t dims_
     int64_t after = 0, before = 0;
     for (k = 0; k < M; ++k) {
         int32_t s = spins[orc_neighbour_index(dims, off, k, x, y, z)];
+        if (s < 0 || s >= Q) continue;   /* a value outside [0, Q) bonds with nothing */
         after += Jp[(int64_t)q_new * Q + s];
         before += Jp[(int64_t)q * Q + s];
     }
@@ -251,13 +259,20 @@ int64_t orc_delta_energy_pair(const int32_t *spins, int nbr, const int32_t dims_
 
 /* n_mcs Monte Carlo steps of red/black Metropolis on a periodic lattice.
  *
- * spins   : int32[N], x fastest, values in [0, Q); updated in place.
+ * spins   : int32[N], x fastest, values in [0, Q) (others are inert, below);
+ *           updated in place.
  * dims    : (Lx, Ly, Lz); Lz = 1 for the 2D neighbourhoods.  Every side even.
  * B       : int32[Q], bulk energy per spin value in 2^-16 units.
  * mcs0    : absolute index of the first step (part of the RNG counter).
  * threads : OpenMP threads over the sites of one half step (any value gives
  *           the same result: sites of one colour share no bond and every
  *           trial reads the state as it was when the half step began).
+ *
+ * A value outside [0, Q) (a caller's buffer may hold one; it names no grain)
+ * is inert: such a site never changes, a neighbour holding one is never
+ * proposed, and its bond contributes the same before and after a trial --
+ * unlike both q and q' under J(1 - delta), nothing with a pair table -- so
+ * it drops out of the energy change.
  *
  * Returns 0, or -1 on bad arguments, -2 if an energy change leaves int32. */
 /* Per-site bulk field (Eq. (7)'s b_i varying inside a grain): E_site[i] in
@@ -312,6 +327,7 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
                 int64_t d;
                 if (orc_colour(nbr, x, y, z) != colour) continue;
                 q = before[i];
+                if (q < 0 || q >= Q) continue;   /* inert: never changes */
                 ctr[0] = (uint32_t)i; ctr[1] = t; ctr[2] = (uint32_t)colour; ctr[3] = 0u;
                 orc_philox4x32_10(ctr, key, r);
                 if (proposal == ORC_PROP_NEIGHBOUR) {
@@ -323,7 +339,7 @@ static int sweep_impl(int32_t *spins, int nbr, int proposal, const int32_t dims_
                     uint32_t s = (uint32_t)(((uint64_t)r[0] * (uint64_t)(Q - 1)) >> 32);
                     q_new = (int32_t)(((int64_t)q + 1 + (int64_t)s) % Q);
                 }
-                if (q_new == q) continue;
+                if (q_new == q || q_new < 0 || q_new >= Q) continue;   /* no change, or an inert value */
                 d = Jp ? orc_delta_energy_pair(before, nbr, dims_in, Jp, Q, B, i, q_new)
                        : orc_delta_energy(before, nbr, dims_in, J_fx, B, i, q_new);
                 if (E_site) d += (int64_t)e_new - (int64_t)before_e[i];
@@ -544,7 +560,7 @@ int orc_texture(const int32_t *spins, int64_t N, int32_t Q, const int32_t *grain
     int64_t *bin_area;
     for (q = 0; q < Q; ++q) areas[q] = 0;
     for (i = 0; i < N; ++i) {
-        if (spins[i] < 0 || spins[i] >= Q) return -1;
+        if (spins[i] < 0 || spins[i] >= Q) continue;   /* inert values belong to no grain */
         areas[spins[i]] += 1;
     }
     for (q = 0; q < Q; ++q) if (areas[q] > 0) ++count;

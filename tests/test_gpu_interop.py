@@ -4,7 +4,8 @@ and network inference on device memory, through the C ABI.
 * a wrapped tensor holds the oracle's spins after every sweep call, whatever
   the parity of the launch count (bit-exact);
 * a wrapped lattice and a library-owned one give the same spins;
-* values outside [0, Q) stay put and are left out of the statistics;
+* values outside [0, Q) follow the oracle's inert rule site for site and are
+  left out of the statistics;
 * bad buffers are rejected before any device work;
 * hmc_mlp_infer on device arrays and a side stream equals hmc_mlp_forward
   and follows the oracle's double-precision network within float32 error.
@@ -75,25 +76,41 @@ def test_wrapped_equals_owned_moore8():
         assert np.array_equal(t.cpu().numpy(), a)
 
 
-def test_out_of_range_values_are_inert():
+@pytest.mark.parametrize("pair", [False, True])
+def test_out_of_range_values_are_inert(pair):
+    """Values outside [0, Q) in a caller's buffer: the GPU follows the
+    oracle's inert rule site for site (such a site never changes, such a
+    neighbour is never proposed; with a pair table it bonds with nothing),
+    and the statistics leave them out."""
     dims, Q, seed, kT = (32, 32), 4, 3, 1.0
-    say("[gpu] wrap out-of-range values")
+    say(f"[gpu] wrap out-of-range values, pair={pair}")
     rng = np.random.default_rng(1)
     s = rng.integers(0, Q, size=(32, 32)).astype(np.int32)
     s[10:14, 6:20] = -1
     s[0, 0] = 99
+    s[20, 5] = 1 << 20
+    B = np.array([0, 3000, -2000, 1000], np.int32)
     t = _tensor_from(s, torch.int32)
     stream = torch.cuda.current_stream().cuda_stream
     with hmc.Lattice(dims, hmc.HMC_VN4, Q, spin=hmc.HMC_I32, stream=stream, dev_ptr=t.data_ptr()) as lat:
+        lat.set_grain_energy(B)
+        if pair:
+            A = np.triu(rng.integers(20000, 90000, size=(Q, Q)), 1)
+            Jp = (A + A.T).astype(np.int32)
+            lat.set_pair_energy(Jp)
+            want = oracle.sweep_pair(s, hmc.HMC_VN4, dims, Jp, B, kT, 20, seed)
+        else:
+            want = oracle.sweep(s, hmc.HMC_VN4, dims, B, kT, 20, seed)
         lat.sweep(kT, 20, seed)
         got = lat.spins()
-        assert np.all(got[10:14, 6:20] == -1) and got[0, 0] == 99
-        inside = (got >= 0) & (got < Q)
-        assert int(inside.sum()) == 32 * 32 - 4 * 14 - 1
-        areas = lat.grain_areas()
-        assert np.array_equal(areas, np.bincount(got[inside], minlength=Q))
+        assert np.array_equal(got, want), f"{int(np.sum(got != want))} sites differ from the oracle"
+        assert np.all(got[10:14, 6:20] == -1) and got[0, 0] == 99 and got[20, 5] == 1 << 20
+        assert not np.array_equal(got, s)
+        areas_o, n_o, mean_o, _ = oracle.texture(want, Q)
+        assert np.array_equal(lat.grain_areas(), areas_o)
         n, mean, _ = lat.texture_stats()
-        assert n == int(np.sum(areas > 0))
+        assert n == n_o and mean == mean_o
+        assert lat.boundary_sites() == oracle.boundary_sites(want, hmc.HMC_VN4, dims, Q)
 
 
 def test_wrap_rejects_bad_buffers():
@@ -139,25 +156,30 @@ def test_mlp_infer_on_device_and_side_stream():
 @pytest.mark.parametrize("pair", [False, True])
 def test_nfold_on_wrapped_tensor_keeps_out_of_range_values(pair):
     """The n-fold way on a caller's buffer that holds values outside [0, Q):
-    those sites never move and are never proposed (as in the sweep), and
-    with pair bond energies they bond with nothing."""
+    spins, event count and clock equal the oracle's under the same inert
+    rule as the sweep."""
     dims, Q = (32, 32), 4
     say(f"[gpu] nfold on a wrapped tensor with out-of-range values, pair={pair}")
     rng = np.random.default_rng(2)
     s = rng.integers(0, Q, size=(32, 32)).astype(np.int32)
     s[10:14, 6:20] = -1
     s[0, 0] = 99
+    B = np.array([0, 3000, -2000, 1000], np.int32)
+    Jp = None
     t = _tensor_from(s, torch.int32)
     stream = torch.cuda.current_stream().cuda_stream
     with hmc.Lattice(dims, hmc.HMC_VN4, Q, spin=hmc.HMC_I32, stream=stream, dev_ptr=t.data_ptr()) as lat:
-        lat.set_grain_energy(np.array([0, 3000, -2000, 1000], np.int32))
+        lat.set_grain_energy(B)
         if pair:
             A = np.triu(rng.integers(20000, 90000, size=(Q, Q)), 1)
-            lat.set_pair_energy((A + A.T).astype(np.int32))
+            Jp = (A + A.T).astype(np.int32)
+            lat.set_pair_energy(Jp)
         lat.nfold(0.8, 3.0, 5)
         torch.cuda.synchronize()
         got = t.cpu().numpy()
         assert np.array_equal(got, lat.spins())
+        want, t_last, n_ev, _ = oracle.nfold(s, hmc.HMC_VN4, dims, B, 0.8, 5, 3.0, Jp=Jp)
+        assert np.array_equal(got, want), f"{int(np.sum(got != want))} sites differ from the oracle"
+        assert lat.nfold_clock()[1:] == (t_last, n_ev)
         assert np.all(got[10:14, 6:20] == -1) and got[0, 0] == 99
-        assert lat.nfold_clock()[2] > 50
-        assert not np.array_equal(got, s)
+        assert n_ev > 50

@@ -63,8 +63,9 @@ def test_texture_identities(orc):
     assert frac.sum() == pytest.approx(binned / s.size, abs=1e-12)
     for b in range(7):
         assert frac[b] == pytest.approx(areas[gb == b].sum() / s.size, abs=1e-15)
-    with pytest.raises(ValueError):
-        orc.texture(np.array([[Q]], np.int32), Q)
+    # a value outside [0, Q) names no grain: left out of the areas
+    a2, ng2, mean2, _ = orc.texture(np.array([[Q, 0, -1, 0]], np.int32), Q)
+    assert a2.sum() == 2 and a2[0] == 2 and ng2 == 1 and mean2 == 4.0
 
 
 def test_sweep_split_equals_whole(orc):
