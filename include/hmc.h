@@ -251,6 +251,35 @@ hmc_status hmc_boundary_sites(hmc_lattice *L, int64_t *n_out);
 /* Wait for all work queued on the lattice's stream. */
 hmc_status hmc_synchronize(hmc_lattice *L);
 
+/* The uint32 threshold table of the Metropolis rule (Sec. 3; Red/Black
+ * passes of Sec. 4 read it) as the host builds it, without a device:
+ * T(d) = min(2^32-1, floor(2^32 exp(-d / (65536 kT)))) for
+ * d = J_fx*dn + dB, rows dn = dn_lo..M (dn_lo the smallest dn with a
+ * positive d), columns dB = -R..R (R = Bmax - Bmin), entry
+ * [(dn - dn_lo) * TW + dB + R], TW = 2R + 1; entries with d <= 0 hold
+ * 2^32 - 1 and are never read.  Each row is cut into nb buckets of bw
+ * columns; bounds[2k] = T at the bucket's largest d, bounds[2k+1] = T at
+ * its smallest positive d, so T over the bucket lies between them (T is
+ * non-increasing in d) and a trial whose r1 is outside [lower, upper) needs
+ * no table read.  layout6 receives (dn_lo, rows, R, TW, nb, bw); table
+ * (rows*TW entries) and bounds (2*rows*nb) may be NULL to query the layout.
+ * Errors: INVAL (NULL layout, kT <= 0 or not finite, M not 4/6/8/26,
+ * J_fx outside [1, 2^24], Bmin > Bmax, a buffer below its cap), RANGE. */
+hmc_status hmc_threshold_table_host(float kT, int32_t M, int32_t J_fx, int32_t Bmin, int32_t Bmax, int32_t *layout6,
+                                    uint32_t *table, uint64_t table_cap, uint32_t *bounds, uint64_t bounds_cap);
+
+/* The threshold table a sweep of L at temperature kT reads, copied back
+ * from device memory after it is built (or reused) exactly as hmc_sweep
+ * builds it.  layout8 receives (kind, dn_lo, rows, R, TW, nb, bw, Dmax):
+ * kind 0 is the bucketed table of hmc_threshold_table_host (Dmax = -1);
+ * kind 1, used with pair bond energies or a per-site field, holds T(d) for
+ * d = 0..Dmax in TW = Dmax + 1 entries (T(0) = 2^32 - 1, d <= 0 accepted
+ * before any read) and no bounds.  table and bounds may be NULL.
+ * Synchronous.  Errors: INVAL (NULL lattice or layout, kT, a buffer below
+ * its cap), RANGE, NOMEM, DEVICE. */
+hmc_status hmc_threshold_table(hmc_lattice *L, float kT, int32_t *layout8, uint32_t *table, uint64_t table_cap,
+                               uint32_t *bounds, uint64_t bounds_cap);
+
 /* ------------------------------------------------------------ ensembles
  * Many independent lattices (uneven sizes, temperatures and seeds) advanced
  * together: one persistent kernel walks a ragged table of every member's

@@ -98,6 +98,16 @@ def threshold(d, kT):
     return int(lib().orc_threshold(int(d), float(kT)))
 
 
+def threshold_many(d, kT):
+    """T(d) of an array of d (uint32; d <= 0 gives 2^32 - 1)."""
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.int64).reshape(-1))
+    out = np.empty(d.size, dtype=np.uint32)
+    f = lib().orc_threshold_many
+    f.argtypes = [C.POINTER(C.c_int64), C.c_int64, C.c_float, C.POINTER(C.c_uint32)]
+    f(_ptr(d, C.c_int64), d.size, float(kT), _ptr(out, C.c_uint32))
+    return out
+
+
 def neighbours_of(nbr, dims, i):
     out = np.empty(26, dtype=np.int64)
     d = _dims3(dims)
@@ -364,6 +374,37 @@ def mcp_one(euler, eps6, seed, sample=0):
     E = lib().orc_mcp_one(_ptr(e, C.c_double), _ptr(s, C.c_double), int(seed), int(sample), C.byref(tc),
                           C.byref(gm), C.byref(K), _ptr(sig, C.c_double))
     return E, tc.value, gm.value, K.value, sig
+
+
+def mcp_run(euler, eps6, seed, K, sample=0, dll=None):
+    """One crystal in an explicit number K of sub-steps: (E_rho, tau_c,
+    accumulated slip, crystal-frame stress[6], candidates per sub-step[K],
+    system picked per sub-step[K], -1 when elastic).  dll: another build of
+    this library (the tests' planted-mistake copies), default this one."""
+    e, s = _f64(euler, 3), _f64(eps6, 6)
+    tc, gm, sig = C.c_double(), C.c_double(), np.zeros(6)
+    nc, picks = np.zeros(K, np.int32), np.zeros(K, np.int32)
+    f = (dll or lib()).orc_mcp_run
+    f.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_uint64, C.c_uint64, C.c_int,
+                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                  C.POINTER(C.c_int32)]
+    f.restype = C.c_double
+    E = f(_ptr(e, C.c_double), _ptr(s, C.c_double), int(seed), int(sample), int(K), C.byref(tc), C.byref(gm),
+          _ptr(sig, C.c_double), _ptr(nc, C.c_int32), _ptr(picks, C.c_int32))
+    return E, tc.value, gm.value, sig, nc, picks
+
+
+def mcp_picks(euler, eps6, seed, n, K, step, sample0=0, dll=None):
+    """(system picked at sub-step `step` of K, candidates at that sub-step)
+    for n sample indices of one crystal."""
+    e, s = _f64(euler, 3), _f64(eps6, 6)
+    picks, nc = np.full(n, -2, np.int32), np.zeros(n, np.int32)
+    f = (dll or lib()).orc_mcp_picks
+    f.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_uint64, C.c_uint64, C.c_int64, C.c_int,
+                  C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    f(_ptr(e, C.c_double), _ptr(s, C.c_double), int(seed), int(sample0), int(n), int(K), int(step),
+      _ptr(picks, C.c_int32), _ptr(nc, C.c_int32))
+    return picks, nc
 
 
 def mcp_solve(euler, eps6, seed, sample0=0, threads=1):

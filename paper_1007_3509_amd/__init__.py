@@ -77,6 +77,10 @@ _SIGS = [
     ("hmc_profile_trials", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("hmc_boundary_sites", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("hmc_synchronize", C.c_int32, [C.c_void_p]),
+    ("hmc_threshold_table_host", C.c_int32, [C.c_float, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64]),
+    ("hmc_threshold_table", C.c_int32, [C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                        C.c_uint64]),
     ("hmc_ensemble_create", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     ("hmc_ensemble_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("hmc_ensemble_get_tiling", C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -311,6 +315,33 @@ def hmc_boundary_sites(h):
 
 def hmc_synchronize(h):
     _check(lib().hmc_synchronize(h))
+
+
+def hmc_threshold_table_host(kT, M, J_fx, Bmin, Bmax):
+    """(layout dict, table uint32[rows*TW], bounds uint32[2*rows*nb]) as the
+    host builds them, no device needed."""
+    lay = np.zeros(6, np.int32)
+    _check(lib().hmc_threshold_table_host(float(kT), int(M), int(J_fx), int(Bmin), int(Bmax), _ptr(lay), None, 0,
+                                          None, 0))
+    dn_lo, rows, R, TW, nb, bw = (int(v) for v in lay)
+    table = np.zeros(rows * TW, np.uint32)
+    bounds = np.zeros(2 * rows * nb, np.uint32)
+    _check(lib().hmc_threshold_table_host(float(kT), int(M), int(J_fx), int(Bmin), int(Bmax), _ptr(lay), _ptr(table),
+                                          table.size, _ptr(bounds), bounds.size))
+    return dict(kind=0, dn_lo=dn_lo, rows=rows, R=R, TW=TW, nb=nb, bw=bw, Dmax=-1), table, bounds
+
+
+def hmc_threshold_table(h, kT):
+    """(layout dict, table, bounds) that a sweep of the lattice at kT reads,
+    copied back from device memory."""
+    lay = np.zeros(8, np.int32)
+    _check(lib().hmc_threshold_table(h, float(kT), _ptr(lay), None, 0, None, 0))
+    kind, dn_lo, rows, R, TW, nb, bw, Dmax = (int(v) for v in lay)
+    table = np.zeros(rows * TW, np.uint32)
+    bounds = np.zeros(2 * rows * nb, np.uint32)
+    _check(lib().hmc_threshold_table(h, float(kT), _ptr(lay), _ptr(table), table.size, _ptr(bounds) if bounds.size else None,
+                                     bounds.size))
+    return dict(kind=kind, dn_lo=dn_lo, rows=rows, R=R, TW=TW, nb=nb, bw=bw, Dmax=Dmax), table, bounds
 
 
 def _handles(lats):

@@ -130,6 +130,13 @@ struct Table {
     bool valid = false;
 };
 uint32_t threshold_value(int64_t d, float kT);
+struct TableLayout {
+    int32_t dn_lo = 0, rows = 0, R = 0, TW = 1, nb = 1, bw = 1;
+};
+// The table and its bucket bounds on the host: rows * TW entries followed by
+// 2 * rows * nb bounds (entries whose d <= 0 hold 2^32 - 1, never read).
+hmc_status table_host(float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax, TableLayout& lay,
+                      std::vector<uint32_t>& host);
 hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax,
                        hipStream_t stream);
 // Threshold table T(d) for every d in [0, Dmax] (pair bond energies,

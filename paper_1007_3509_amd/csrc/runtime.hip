@@ -93,11 +93,10 @@ namespace {
 constexpr size_t kTableCapBytes = 256ull << 20;
 }
 
-hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax, hipStream_t stream) {
-    uint32_t bits;
-    std::memcpy(&bits, &kT, sizeof bits);
-    if (tab.valid && tab.kT_bits == bits && tab.Bmin == Bmin && tab.Bmax == Bmax) return HMC_OK;
+hmc_status table_host(float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax, TableLayout& lay,
+                      std::vector<uint32_t>& host) {
     const int64_t R = (int64_t)Bmax - Bmin;
+    if (R < 0) return fail(HMC_E_INVAL, "Bmax < Bmin");
     int64_t dn_lo = -M;
     while (dn_lo <= M && (int64_t)J_fx * dn_lo + R <= 0) ++dn_lo;
     if (dn_lo > M) dn_lo = M;   // no positive d possible; keep one row
@@ -111,7 +110,7 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     const size_t bytes = (entries + nbound) * sizeof(uint32_t);
     if (bytes > kTableCapBytes)
         return fail(HMC_E_RANGE, "threshold table would need " + std::to_string(bytes) + " bytes");
-    std::vector<uint32_t> host(entries + nbound, 0xFFFFFFFFu);
+    host.assign(entries + nbound, 0xFFFFFFFFu);
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t dn = dn_lo + r;
         for (int64_t j = 0; j < TW; ++j) {
@@ -129,6 +128,24 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
             }
         }
     }
+    lay.dn_lo = (int32_t)dn_lo;
+    lay.rows = (int32_t)rows;
+    lay.R = (int32_t)R;
+    lay.TW = (int32_t)TW;
+    lay.nb = (int32_t)nb;
+    lay.bw = (int32_t)bw;
+    return HMC_OK;
+}
+
+hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, int32_t Bmax, hipStream_t stream) {
+    uint32_t bits;
+    std::memcpy(&bits, &kT, sizeof bits);
+    if (tab.valid && tab.kT_bits == bits && tab.Bmin == Bmin && tab.Bmax == Bmax) return HMC_OK;
+    TableLayout lay;
+    std::vector<uint32_t> host;
+    HMC_TRY(table_host(kT, M, J_fx, Bmin, Bmax, lay, host));
+    const size_t entries = (size_t)lay.rows * (size_t)lay.TW;
+    const size_t bytes = host.size() * sizeof(uint32_t);
     if (tab.bytes < bytes) {
         free_table(tab);
         void* p = nullptr;
@@ -137,14 +154,14 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
         tab.bytes = bytes;
     }
     tab.bounds = tab.dev + entries;
-    tab.nb = (int32_t)nb;
-    tab.bw = (int32_t)bw;
+    tab.nb = lay.nb;
+    tab.bw = lay.bw;
     HMC_HIP(hipMemcpyAsync(tab.dev, host.data(), bytes, hipMemcpyHostToDevice, stream));
     HMC_HIP(hipStreamSynchronize(stream));
-    tab.dn_lo = (int32_t)dn_lo;
-    tab.rows = (int32_t)rows;
-    tab.R = (int32_t)R;
-    tab.TW = (int32_t)TW;
+    tab.dn_lo = lay.dn_lo;
+    tab.rows = lay.rows;
+    tab.R = lay.R;
+    tab.TW = lay.TW;
     tab.kT_bits = bits;
     tab.Bmin = Bmin;
     tab.Bmax = Bmax;
@@ -313,7 +330,7 @@ using namespace hmc;
 
 extern "C" {
 
-int32_t hmc_abi_version(void) { return 4; }
+int32_t hmc_abi_version(void) { return 5; }
 
 const char* hmc_last_error(void) { return g_error.c_str(); }
 
@@ -729,6 +746,67 @@ hmc_status hmc_profile_read(hmc_lattice* L, double* kernel_ms, int64_t* launches
 hmc_status hmc_synchronize(hmc_lattice* L) {
     g_error.clear();
     if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    HMC_HIP(hipStreamSynchronize(L->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_threshold_table_host(float kT, int32_t M, int32_t J_fx, int32_t Bmin, int32_t Bmax, int32_t* layout6,
+                                    uint32_t* table, uint64_t table_cap, uint32_t* bounds, uint64_t bounds_cap) {
+    g_error.clear();
+    if (!layout6) return fail(HMC_E_INVAL, "layout is NULL");
+    if (!(kT > 0.0f) || !std::isfinite(kT)) return fail(HMC_E_INVAL, "kT must be positive and finite");
+    if (M != 4 && M != 6 && M != 8 && M != 26) return fail(HMC_E_INVAL, "M must be 4, 6, 8 or 26");
+    if (J_fx < 1 || J_fx > (1 << 24)) return fail(HMC_E_INVAL, "J_fx must be in [1, 2^24]");
+    if (Bmin > Bmax) return fail(HMC_E_INVAL, "Bmin > Bmax");
+    if ((int64_t)J_fx * M + 2 * std::max(std::llabs((int64_t)Bmin), std::llabs((int64_t)Bmax)) >= (1ll << 31))
+        return fail(HMC_E_RANGE, "J_fx * M + 2 max|B| must stay below 2^31");
+    TableLayout lay;
+    std::vector<uint32_t> host;
+    HMC_TRY(table_host(kT, M, J_fx, Bmin, Bmax, lay, host));
+    const int32_t v[6] = {lay.dn_lo, lay.rows, lay.R, lay.TW, lay.nb, lay.bw};
+    std::memcpy(layout6, v, sizeof v);
+    const size_t entries = (size_t)lay.rows * (size_t)lay.TW, nbound = 2 * (size_t)lay.rows * (size_t)lay.nb;
+    if (table) {
+        if (table_cap < entries) return fail(HMC_E_INVAL, "table buffer smaller than rows * TW");
+        std::memcpy(table, host.data(), entries * 4);
+    }
+    if (bounds) {
+        if (bounds_cap < nbound) return fail(HMC_E_INVAL, "bounds buffer smaller than 2 * rows * nb");
+        std::memcpy(bounds, host.data() + entries, nbound * 4);
+    }
+    return HMC_OK;
+}
+
+hmc_status hmc_threshold_table(hmc_lattice* L, float kT, int32_t* layout8, uint32_t* table, uint64_t table_cap,
+                               uint32_t* bounds, uint64_t bounds_cap) {
+    g_error.clear();
+    if (!L || !layout8) return fail(HMC_E_INVAL, "NULL argument");
+    if (!(kT > 0.0f) || !std::isfinite(kT)) return fail(HMC_E_INVAL, "kT must be positive and finite");
+    if (L->pair || L->field) {
+        HMC_TRY(build_direct_table(L, kT));
+        const int32_t v[8] = {1, 0, 1, 0, L->Tg_Dmax + 1, 0, 0, L->Tg_Dmax};
+        std::memcpy(layout8, v, sizeof v);
+        const size_t entries = (size_t)L->Tg_Dmax + 1;
+        if (table) {
+            if (table_cap < entries) return fail(HMC_E_INVAL, "table buffer smaller than Dmax + 1");
+            HMC_HIP(hipMemcpyAsync(table, L->d_Tg, entries * 4, hipMemcpyDeviceToHost, L->stream));
+        }
+        HMC_HIP(hipStreamSynchronize(L->stream));
+        return HMC_OK;
+    }
+    HMC_TRY(build_table(L->table, kT, L->M, L->desc.J_fx, L->Bmin, L->Bmax, L->stream));
+    const Table& t = L->table;
+    const int32_t v[8] = {0, t.dn_lo, t.rows, t.R, t.TW, t.nb, t.bw, -1};
+    std::memcpy(layout8, v, sizeof v);
+    const size_t entries = (size_t)t.rows * (size_t)t.TW, nbound = 2 * (size_t)t.rows * (size_t)t.nb;
+    if (table) {
+        if (table_cap < entries) return fail(HMC_E_INVAL, "table buffer smaller than rows * TW");
+        HMC_HIP(hipMemcpyAsync(table, t.dev, entries * 4, hipMemcpyDeviceToHost, L->stream));
+    }
+    if (bounds) {
+        if (bounds_cap < nbound) return fail(HMC_E_INVAL, "bounds buffer smaller than 2 * rows * nb");
+        HMC_HIP(hipMemcpyAsync(bounds, t.bounds, nbound * 4, hipMemcpyDeviceToHost, L->stream));
+    }
     HMC_HIP(hipStreamSynchronize(L->stream));
     return HMC_OK;
 }
