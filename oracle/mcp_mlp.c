@@ -139,17 +139,32 @@ int orc_mcp_select(const double *p, int n, double R)
     return n - 1;
 }
 
-/* One crystal.  eps6 = (e11, e22, e33, e23, e13, e12), tensor shear
- * components, sample frame.  Returns E_rho (MPa); tau_c, gamma and the
- * number of sub-steps through the optional outputs. */
-double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, uint64_t sample,
-                   double *tauc_out, double *gamma_out, int *steps_out, double *sig_out)
+/* Sub-steps for a strain: K = ceil(max|eps_ij| / 1e-5), in [1, 200]. */
+int orc_mcp_substeps(const double eps6[6])
+{
+    double maxabs = 0.0;
+    int i, K;
+    for (i = 0; i < 6; ++i) if (fabs(eps6[i]) > maxabs) maxabs = fabs(eps6[i]);
+    K = (int)ceil(maxabs / 1e-5);
+    if (K < 1) K = 1;
+    if (K > 200) K = 200;
+    return K;
+}
+
+/* One crystal driven to the strain eps6 = (e11, e22, e33, e23, e13, e12)
+ * (tensor shear components, sample frame) in K equal sub-steps.  Returns
+ * E_rho (MPa); tau_c, the accumulated slip and the crystal-frame stress
+ * (s11, s22, s33, s23, s13, s12) through the optional outputs, and, for the
+ * tests, the number of candidate systems of each sub-step (ncand_out[K])
+ * and the system picked at it (picks_out[K], -1 when elastic). */
+double orc_mcp_run(const double euler[3], const double eps6[6], uint64_t seed, uint64_t sample, int K,
+                   double *tauc_out, double *gamma_out, double *sig_out, int *ncand_out, int *picks_out)
 {
     double n[12][3], d[12][3], P[12][3][3], CP[12][3][3], PCP[12];
     double g[3][3], es[3][3], ec[3][3], de[3][3], sig[3][3];
-    double maxabs = 0.0, gamma = 0.0, tc = MCP_TAU0;
+    double gamma = 0.0, tc = MCP_TAU0;
     uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
-    int a, i, j, k, K, step;
+    int a, i, j, k, step;
     mcp_systems(n, d);
     for (a = 0; a < 12; ++a) {
         for (i = 0; i < 3; ++i)
@@ -161,7 +176,6 @@ double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, u
     es[1][2] = es[2][1] = eps6[3];
     es[0][2] = es[2][0] = eps6[4];
     es[0][1] = es[1][0] = eps6[5];
-    for (i = 0; i < 6; ++i) if (fabs(eps6[i]) > maxabs) maxabs = fabs(eps6[i]);
     bunge(euler, g);
     for (i = 0; i < 3; ++i)          /* crystal-frame strain g es g^T */
         for (j = 0; j < 3; ++j) {
@@ -171,9 +185,7 @@ double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, u
                 for (q = 0; q < 3; ++q) acc += g[i][p] * es[p][q] * g[j][q];
             ec[i][j] = acc;
         }
-    K = (int)ceil(maxabs / 1e-5);
     if (K < 1) K = 1;
-    if (K > 200) K = 200;
     for (i = 0; i < 3; ++i)
         for (j = 0; j < 3; ++j) { de[i][j] = ec[i][j] / K; sig[i][j] = 0.0; }
 
@@ -185,6 +197,8 @@ double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, u
             for (j = 0; j < 3; ++j) str[i][j] = sig[i][j] + dsig[i][j];
         for (a = 0; a < 12; ++a)
             if (fabs(ddot(str, P[a])) > tc) cand[nc++] = a;
+        if (ncand_out) ncand_out[step - 1] = nc;
+        if (picks_out) picks_out[step - 1] = -1;
         if (nc == 0) {
             memcpy(sig, str, sizeof sig);
             continue;
@@ -211,6 +225,7 @@ double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, u
             orc_philox4x32_10(ctr, key, r);
             R = (double)((((uint64_t)r[0] << 32) | r[1]) >> 11) * (1.0 / 9007199254740992.0);
             pick = orc_mcp_select(p, nc, R);
+            if (picks_out) picks_out[step - 1] = cand[pick];
             {
                 double tau = ddot(str, P[cand[pick]]);
                 double sgn = tau > 0.0 ? 1.0 : -1.0;
@@ -223,12 +238,45 @@ double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, u
     }
     if (tauc_out) *tauc_out = tc;
     if (gamma_out) *gamma_out = gamma;
-    if (steps_out) *steps_out = K;
     if (sig_out) {   /* crystal frame, (s11, s22, s33, s23, s13, s12) */
         sig_out[0] = sig[0][0]; sig_out[1] = sig[1][1]; sig_out[2] = sig[2][2];
         sig_out[3] = sig[1][2]; sig_out[4] = sig[0][2]; sig_out[5] = sig[0][1];
     }
     return 2.0 * tc * tc / orc_mcp_shear_modulus();
+}
+
+/* One crystal with the sub-step rule above.  Returns E_rho (MPa); tau_c,
+ * gamma, the number of sub-steps and the stress through the optional
+ * outputs. */
+double orc_mcp_one(const double euler[3], const double eps6[6], uint64_t seed, uint64_t sample,
+                   double *tauc_out, double *gamma_out, int *steps_out, double *sig_out)
+{
+    int K = orc_mcp_substeps(eps6);
+    if (steps_out) *steps_out = K;
+    return orc_mcp_run(euler, eps6, seed, sample, K, tauc_out, gamma_out, sig_out, NULL, NULL);
+}
+
+/* The system picked at sub-step `step` (1-based) of K for one crystal under
+ * n sample indices sample0 .. sample0 + n - 1 (each draws its own R of
+ * Eq. (2)); for the tests of Eq. (1). */
+void orc_mcp_picks(const double euler[3], const double eps6[6], uint64_t seed, uint64_t sample0, int64_t n, int K,
+                   int step, int *pick_out, int *ncand_out)
+{
+    int64_t s;
+    int *picks = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    int *nc = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    if (!picks || !nc || step < 1 || step > K) {
+        free(picks);
+        free(nc);
+        return;
+    }
+    for (s = 0; s < n; ++s) {
+        orc_mcp_run(euler, eps6, seed, sample0 + (uint64_t)s, K, NULL, NULL, NULL, nc, picks);
+        pick_out[s] = picks[step - 1];
+        if (ncand_out) ncand_out[s] = nc[step - 1];
+    }
+    free(picks);
+    free(nc);
 }
 
 void orc_mcp_solve(const double *euler, const double *eps6, int64_t n, uint64_t seed, uint64_t sample0,
