@@ -58,10 +58,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="schmid_2d_1024", choices=sorted(WORKLOADS) + list(SPECIAL))
+    ap.add_argument("--workload", default="schmid_3d_256", choices=sorted(WORKLOADS) + list(SPECIAL))
     ap.add_argument("--mcs", type=int, default=0, help="override MC steps per job")
     ap.add_argument("--tiling", default="", help="tx,ty,tz,k (default: library choice)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
@@ -88,11 +88,32 @@ def measured_profile(workload, tiling, kernel="sweep_tile_kernel"):
     return {k: float(fields[k]) for k in keys[:2] if k in fields}
 
 
+def host_threads():
+    """Threads the oracle may use (the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when that is set) and a description of the host."""
+    affinity = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(affinity, int(omp)) if omp.isdigit() and int(omp) > 0 else affinity
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, {"host_cpus": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model}
+
+
 def cpu_baseline(w, start, n_mcs, budget_s, gpu_check, field=None):
-    """The oracle, as it stands, on the same job from the same initial state."""
+    """The oracle, as it stands, on the same job from the same initial state:
+    as many MC steps of the job as the budget allows on every host thread, and
+    the first steps of that run again on one thread (reference semantics),
+    which must give the same spins."""
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, host = host_threads()
     pair = w.extra.get("pair")
     extra = {}
     if pair:
@@ -100,48 +121,57 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check, field=None):
         Jp = oracle.pair_table(w.euler, *pair)
         extra["pair_table_max_abs_diff_gpu_vs_oracle"] = int(np.max(np.abs(gpu_check.table().astype(np.int64) - Jp)))
 
-        def run(n, th):
-            return oracle.sweep_pair(start, w.nbr, w.dims, Jp, w.B, w.kT, n, w.sweep_seed, threads=th)
+        def run(state, n, th, mcs0):
+            return oracle.sweep_pair(state, w.nbr, w.dims, Jp, w.B, w.kT, n, w.sweep_seed, mcs0=mcs0, threads=th)
+        spins_of = lambda state: state  # noqa: E731
+        state0 = start
     elif field is not None:
         Jp = None
         zeros = np.zeros(w.n_grains, np.int32)
 
-        def run(n, th):
-            return oracle.sweep_field(start, field, w.extra["field_rule"], w.nbr, w.dims, zeros, w.kT, n,
-                                      w.sweep_seed, threads=th)[0]
+        def run(state, n, th, mcs0):
+            return oracle.sweep_field(state[0], state[1], w.extra["field_rule"], w.nbr, w.dims, zeros, w.kT, n,
+                                      w.sweep_seed, mcs0=mcs0, threads=th)
+        spins_of = lambda state: state[0]  # noqa: E731
+        state0 = (start, field)
     else:
         Jp = None
 
-        def run(n, th):
-            return oracle.sweep(start, w.nbr, w.dims, w.B, w.kT, n, w.sweep_seed, threads=th)
-    probe = 2
+        def run(state, n, th, mcs0):
+            return oracle.sweep(state, w.nbr, w.dims, w.B, w.kT, n, w.sweep_seed, mcs0=mcs0, threads=th)
+        spins_of = lambda state: state  # noqa: E731
+        state0 = start
     t0 = time.perf_counter()
-    run(probe, threads)
-    per_mcs = (time.perf_counter() - t0) / probe
-    sample = int(max(1, min(n_mcs, budget_s / max(per_mcs, 1e-9))))
+    run(state0, 1, threads, 0)
+    per_mcs = time.perf_counter() - t0
     t0 = time.perf_counter()
-    out = run(sample, threads)
-    dt = time.perf_counter() - t0
-    exact = bool(np.array_equal(gpu_check(sample, Jp), out))
-    # single-thread reference semantics on a quarter of the budget
-    t0 = time.perf_counter()
-    run(1, 1)
+    run(state0, 1, 1, 0)
     per1 = time.perf_counter() - t0
-    sample1 = int(max(1, min(n_mcs, budget_s / 4 / max(per1, 1e-9))))
+    sample = int(max(1, min(n_mcs, budget_s / max(per_mcs, 1e-9))))
+    # the single-thread leg repeats the first s1 steps (about a third of the budget)
+    s1 = int(max(1, min(sample, budget_s / 3 / max(per1, 1e-9))))
     t0 = time.perf_counter()
-    out1 = run(sample1, 1)
+    mid = run(state0, s1, threads, 0)
+    out = run(mid, sample - s1, threads, s1) if sample > s1 else mid
+    dt = time.perf_counter() - t0
+    exact = bool(np.array_equal(gpu_check(sample, Jp), spins_of(out)))
+    t0 = time.perf_counter()
+    one = run(state0, s1, 1, 0)
     dt1 = time.perf_counter() - t0
-    same_1t = bool(np.array_equal(out1, out)) if sample1 == sample else None
+    same_1t = bool(np.array_equal(spins_of(one), spins_of(mid)))
     return {
         "value": w.n_sites * sample / dt,
         "unit": "site-updates/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{w.name}: first {sample} of {n_mcs} MC steps from the same initial grains "
-                  f"({w.n_sites * sample:.3g} site updates, {dt:.1f} s)",
+                  f"({w.n_sites * sample:.3g} site updates, {dt:.1f} s on {threads} threads)",
+        **host,
         "gpu_bit_exact_on_sample": exact,
-        "single_core": {"value": w.n_sites * sample1 / dt1, "sample_mcs": sample1,
-                        "same_as_threaded": same_1t},
+        "single_core": {"value": w.n_sites * s1 / dt1, "sample_mcs": s1,
+                        "same_as_threaded": same_1t,
+                        "note": "the first sample_mcs steps on one thread against the threaded run's state "
+                                "after the same steps"},
         **extra,
     }
 
@@ -239,7 +269,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int16" if s_bytes == 2 else "int32",
         "data": "synthetic",
         "config": {
             "workload": w.name,
@@ -298,7 +328,7 @@ def main():
 def _line(metric, value, args, ms, config, **extra):
     out = {"metric": metric, "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": config}
+           "vs_baseline": None, "dtype": "int16", "data": "synthetic", "config": config}
     out.update(extra)
     print(json.dumps(out), flush=True)
 
@@ -387,7 +417,7 @@ def bench_ensemble(args, hmc):
     if not args.no_cpu_baseline:
         # the oracle on whole members, smallest first, as many as the budget allows
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads, host = host_threads()
         order = sorted(range(len(members)), key=lambda i: members[i].n_sites)
         t0 = time.perf_counter()
         done, sites, exact = 0, 0, True
@@ -401,7 +431,7 @@ def bench_ensemble(args, hmc):
             sites += w.n_sites
         dt = time.perf_counter() - t0
         extra["cpu_baseline"] = {"value": sites * n_mcs / dt, "unit": "site-updates/s", "cores": threads,
-                                 "kind": "oracle",
+                                 "kind": "oracle", **host,
                                  "sample": f"the {done} smallest of {len(members)} members, whole {n_mcs}-MCS runs "
                                            f"({sites * n_mcs:.3g} site updates, {dt:.1f} s)",
                                  "gpu_bit_exact_on_sample": exact}
@@ -514,7 +544,7 @@ def bench_nfold(args, hmc):
         "metric": "Potts site-MC-steps/s with the n-fold way, 1024-lattice batch, 1 MI355X, bit-exact vs oracle",
         "value": site_mcs / nf_s, "unit": "site-MC-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": nf_s * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "int16", "data": "synthetic",
         "config": {"workload": args.workload, "lattices": len(members), "lattice": "128x128",
                    "neighbourhood": "VN4", "grains": members[0].n_grains, "kT": float(kT[0]),
                    "mcs_per_step": mcs},
@@ -621,11 +651,11 @@ def bench_learned(args, hmc):
         # the method without the network on the host: the oracle's solver for
         # one query (every grain under the last strain of the path)
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads, host = host_threads()
         tiled = np.tile(synth.uniaxial_strain(n_q, n_q), (w.n_grains, 1))
         t0 = time.perf_counter()
         oracle.mcp_solve(euler, tiled, seed=0, threads=threads)
-        cpu = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms per query", "cores": threads, "kind": "oracle",
+        cpu = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms per query", "cores": threads, "kind": "oracle", **host,
                "sample": f"crystal-plasticity solve of the {w.n_grains} grains under the final strain"}
     su = w.n_sites * n_mcs
     _line("Potts site-updates/s with learned stored energy (re-queried every 10 MCS), 1 MI355X",

@@ -8,6 +8,7 @@ import re
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -61,3 +62,35 @@ def test_every_profile_names_the_command_that_made_it():
         text = open(os.path.join(ROOT, "profiles", name)).read()
         assert "rocprofv3 --kernel-trace --stats" in text, name
         assert "bench.py" in text, name
+
+
+def test_cpu_baseline_reports_host_and_checks_single_thread(orc):
+    """The CPU leg on a small job: every MC step of the job within the
+    budget, the host's CPUs named, and the single-thread prefix equal to the
+    threaded run's state after the same steps; a check that returns the
+    oracle's own spins is reported bit-exact, any other is not."""
+    import synth
+
+    w = synth.voronoi_2d_64()
+    start = orc.voronoi(w.dims, w.n_grains, w.voronoi_seed)
+    want = orc.sweep(start, w.nbr, w.dims, w.B, w.kT, w.n_mcs, w.sweep_seed)
+    calls = []
+
+    def gpu_check(sample, Jp=None):
+        calls.append(sample)
+        return orc.sweep(start, w.nbr, w.dims, w.B, w.kT, sample, w.sweep_seed)
+
+    out = bench.cpu_baseline(w, start, w.n_mcs, 30.0, gpu_check)
+    assert calls == [w.n_mcs] and np.array_equal(gpu_check(w.n_mcs), want)
+    assert out["gpu_bit_exact_on_sample"] is True
+    assert out["single_core"]["same_as_threaded"] is True
+    assert 1 <= out["single_core"]["sample_mcs"] <= w.n_mcs
+    assert out["cores"] >= 1 and out["host_cpus"] >= out["affinity_cpus"] >= 1
+    assert f"first {w.n_mcs} of {w.n_mcs}" in out["sample"]
+
+    def wrong(sample, Jp=None):
+        s = gpu_check(sample).copy()
+        s[0] = (s[0] + 1) % w.n_grains
+        return s
+
+    assert bench.cpu_baseline(w, start, w.n_mcs, 30.0, wrong)["gpu_bit_exact_on_sample"] is False
