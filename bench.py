@@ -141,9 +141,10 @@ def cpu_baseline(w, start, n_mcs, budget_s, gpu_check, field=None):
             return oracle.sweep(state, w.nbr, w.dims, w.B, w.kT, n, w.sweep_seed, mcs0=mcs0, threads=th)
         spins_of = lambda state: state  # noqa: E731
         state0 = start
+    run(state0, 1, threads, 0)          # warm the thread pool and caches
     t0 = time.perf_counter()
-    run(state0, 1, threads, 0)
-    per_mcs = time.perf_counter() - t0
+    run(state0, 2, threads, 0)
+    per_mcs = (time.perf_counter() - t0) / 2
     t0 = time.perf_counter()
     run(state0, 1, 1, 0)
     per1 = time.perf_counter() - t0
@@ -592,18 +593,20 @@ def bench_learned(args, hmc):
     MC steps (50 queries over 500 steps): the trained network (with audit)
     against the crystal-plasticity solver in the loop."""
     w = synth.schmid_3d_256()
+    R = synth.LEARNED
     n_mcs = args.mcs or w.n_mcs
-    every = 10
+    every = R["every"]
     n_q = n_mcs // every
     # training data from the solver (outside the timed region)
-    n_train, n_test = 1000000, 20000
-    eu, ep = synth.crystal_inputs(n_train + n_test, 5005)
+    n_train, n_test = R["n_train"], R["n_test"]
+    eu, ep = synth.crystal_inputs(n_train + n_test, R["data_seed"])
     t0 = time.perf_counter()
-    Ey = hmc.hmc_mcp_solve(eu, ep, seed=50)
+    Ey = hmc.hmc_mcp_solve(eu, ep, seed=R["solver_seed"])
     t_gen = time.perf_counter() - t0
-    M = hmc.hmc_mlp_create(7)
+    M = hmc.hmc_mlp_create(R["init_seed"])
     t0 = time.perf_counter()
-    loss = hmc.hmc_mlp_train(M, eu[:n_train], ep[:n_train], Ey[:n_train], epochs=50, batch=2048, lr=5e-3, seed=1)
+    loss = hmc.hmc_mlp_train(M, eu[:n_train], ep[:n_train], Ey[:n_train], epochs=R["epochs"], batch=R["batch"],
+                             lr=R["lr"], seed=R["train_seed"])
     t_train = time.perf_counter() - t0
     pred = hmc.hmc_mlp_predict(M, eu[n_train:], ep[n_train:])
     rel = np.abs(pred - Ey[n_train:]) / Ey[n_train:]
@@ -619,7 +622,8 @@ def bench_learned(args, hmc):
         for k in range(n_q):
             q0 = time.perf_counter()
             _, used, err = hmc.hmc_surrogate_update(lat, M, euler, synth.uniaxial_strain(k + 1, n_q), scale,
-                                                    mode=mode, n_audit=64, audit_tol=0.25, seed=k)
+                                                    mode=mode, n_audit=R["n_audit"], audit_tol=R["audit_tol"],
+                                                    seed=k)
             tq += time.perf_counter() - q0
             fallbacks += int(used)
             errs.append(err)
