@@ -203,6 +203,27 @@ hmc_status hmc_texture_stats(hmc_lattice *L, const int32_t *grain_bin, int32_t n
 /* Area (site count) of every spin value 0..Q-1 into int64[Q].  Synchronous. */
 hmc_status hmc_grain_areas(hmc_lattice *L, int64_t *areas_out);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the statistics of
+ * hmc_texture_stats for n_sites spins in the caller's device buffer
+ * dev_spins (spin = HMC_I16 or HMC_I32, values outside [0, n_grains) not
+ * counted), with no device or host allocation.  The working memory is a
+ * fixed array inside the library, one per device (about 0.5 MiB, held until
+ * the process ends), which bounds n_grains <= HMC_STATIC_MAX_GRAINS and
+ * n_bins <= HMC_STATIC_MAX_BINS; larger requests fail with HMC_E_INVAL
+ * before any device work.  Runs on the current device, on `stream` (NULL:
+ * the default stream), which must belong to that device.  grain_bin: host
+ * int32[n_grains] in [-1, n_bins) (NULL when n_bins == 0); outputs as
+ * hmc_texture_stats.  Synchronous.  Every call on a device uses that
+ * device's one array: calls that overlap in time on one device (other
+ * threads, other streams) race and must be serialised by the caller.
+ * Errors: INVAL (NULL, sizes, not device memory, misaligned), DEVICE. */
+#define HMC_STATIC_MAX_GRAINS 65536
+#define HMC_STATIC_MAX_BINS 1024
+hmc_status hmc_texture_stats_static(const void *dev_spins, int32_t spin, uint64_t n_sites, int32_t n_grains,
+                                    const int32_t *grain_bin, int32_t n_bins, void *stream,
+                                    int32_t *n_grains_out, double *mean_area_out, double *frac_out);
+
 /* Copy the spins to / from host memory (bytes must equal N * spin size).
  * set_spins rejects values outside [0, Q).  Synchronous. */
 hmc_status hmc_get_spins(hmc_lattice *L, void *host_dst, uint64_t bytes);

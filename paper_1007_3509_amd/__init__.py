@@ -63,6 +63,8 @@ _SIGS = [
     ("hmc_texture_stats", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double), C.c_void_p]),
     ("hmc_grain_areas", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("hmc_texture_stats_static", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint64, C.c_int32, C.c_void_p, C.c_int32,
+                                             C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p]),
     ("hmc_get_spins", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64]),
     ("hmc_set_spins", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64]),
     ("hmc_snapshot", C.c_int32, [C.c_void_p]),
@@ -241,6 +243,23 @@ def hmc_texture_stats(h, grain_bin=None, n_bins=0):
     gb = None if grain_bin is None else np.ascontiguousarray(np.asarray(grain_bin, dtype=np.int32))
     _check(lib().hmc_texture_stats(h, None if gb is None else _ptr(gb), int(n_bins), C.byref(ng), C.byref(mean),
                                    _ptr(frac)))
+    return int(ng.value), float(mean.value), frac[:int(n_bins)].copy()
+
+
+HMC_STATIC_MAX_GRAINS, HMC_STATIC_MAX_BINS = 65536, 1024
+
+
+def hmc_texture_stats_static(dev_spins, spin, n_sites, n_grains, grain_bin=None, n_bins=0, stream=None):
+    """Grain statistics of n_sites spins in device memory at address
+    dev_spins, without any allocation: (n_grains present, mean area, frac)."""
+    ng = C.c_int32()
+    mean = C.c_double()
+    frac = np.zeros(max(int(n_bins), 1), dtype=np.float64)
+    gb = None if grain_bin is None else np.ascontiguousarray(np.asarray(grain_bin, dtype=np.int32))
+    _check(lib().hmc_texture_stats_static(C.c_void_p(int(dev_spins) if dev_spins else None), int(spin), int(n_sites),
+                                          int(n_grains), None if gb is None else _ptr(gb), int(n_bins),
+                                          None if stream is None else C.c_void_p(int(stream)), C.byref(ng),
+                                          C.byref(mean), _ptr(frac)))
     return int(ng.value), float(mean.value), frac[:int(n_bins)].copy()
 
 

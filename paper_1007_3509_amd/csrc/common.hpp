@@ -262,6 +262,13 @@ hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
 hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas
 hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins);
+// The same two steps on raw device buffers: per-spin areas of N spins
+// (values outside [0, Q) not counted) into d_areas[Q], then the
+// present-grain count and per-bin areas into d_stats[1 + n_bins] (d_gbin may
+// be null when n_bins is 0).  Both clear their outputs with a kernel first.
+hmc_status launch_areas(const void* spins, bool i16, uint64_t N, uint32_t Q, uint32_t* d_areas, hipStream_t stream);
+hmc_status launch_bins(const uint32_t* d_areas, int32_t Q, const int32_t* d_gbin, int32_t n_bins,
+                       unsigned long long* d_stats, hipStream_t stream);
 int lds_limit_bytes();
 hmc_status settle_borrowed(hmc_lattice* L);
 

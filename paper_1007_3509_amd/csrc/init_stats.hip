@@ -192,6 +192,13 @@ bin_stats_kernel(const uint32_t* __restrict__ areas, int32_t Q, const int32_t* _
             if (bins[b]) atomicAdd(&out[1 + b], bins[b]);
 }
 
+// Zero n 32-bit words (a kernel rather than a memset node, so that the
+// statistics stay correct inside a caller's captured graph).
+__global__ void __launch_bounds__(256) clear_kernel(uint32_t* __restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 int grid_for(uint64_t n, int threads, int cap) {
     uint64_t g = (n + threads - 1) / threads;
     if (g > (uint64_t)cap) g = cap;
@@ -289,18 +296,30 @@ hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed) {
     return HMC_OK;
 }
 
-hmc_status launch_histogram(hmc_lattice* L) {
-    HMC_HIP(hipMemsetAsync(L->d_areas, 0, (size_t)L->Q * sizeof(uint32_t), L->stream));
-    const uint64_t N = (uint64_t)L->N;
+hmc_status launch_areas(const void* spins, bool i16, uint64_t N, uint32_t Q, uint32_t* d_areas, hipStream_t stream) {
+    clear_kernel<<<grid_for(Q, 256, 256), 256, 0, stream>>>(d_areas, Q);
     const int grid = grid_for(N, kHistThreads, 4096);
-    if (L->desc.spin == HMC_I16)
-        histogram_kernel<int16_t><<<grid, kHistThreads, 0, L->stream>>>((const int16_t*)L->spins[L->cur], N,
-                                                                          (uint32_t)L->Q, L->d_areas);
+    if (i16)
+        histogram_kernel<int16_t><<<grid, kHistThreads, 0, stream>>>((const int16_t*)spins, N, Q, d_areas);
     else
-        histogram_kernel<int32_t><<<grid, kHistThreads, 0, L->stream>>>((const int32_t*)L->spins[L->cur], N,
-                                                                          (uint32_t)L->Q, L->d_areas);
+        histogram_kernel<int32_t><<<grid, kHistThreads, 0, stream>>>((const int32_t*)spins, N, Q, d_areas);
     HMC_HIP(hipGetLastError());
     return HMC_OK;
+}
+
+hmc_status launch_bins(const uint32_t* d_areas, int32_t Q, const int32_t* d_gbin, int32_t n_bins,
+                       unsigned long long* d_stats, hipStream_t stream) {
+    const uint64_t words = (uint64_t)(1 + n_bins) * 2;
+    clear_kernel<<<grid_for(words, 256, 64), 256, 0, stream>>>(reinterpret_cast<uint32_t*>(d_stats), words);
+    const int grid = grid_for((uint64_t)Q, kBinThreads, 1024);
+    bin_stats_kernel<<<grid, kBinThreads, 0, stream>>>(d_areas, Q, d_gbin, n_bins, d_stats);
+    HMC_HIP(hipGetLastError());
+    return HMC_OK;
+}
+
+hmc_status launch_histogram(hmc_lattice* L) {
+    return launch_areas(L->spins[L->cur], L->desc.spin == HMC_I16, (uint64_t)L->N, (uint32_t)L->Q, L->d_areas,
+                        L->stream);
 }
 
 hmc_status launch_boundary_count(hmc_lattice* L) {
@@ -330,11 +349,7 @@ hmc_status launch_boundary_count(hmc_lattice* L) {
 }
 
 hmc_status launch_bin_stats(hmc_lattice* L, const int32_t* d_gbin, int32_t n_bins) {
-    HMC_HIP(hipMemsetAsync(L->d_stats, 0, (size_t)(1 + n_bins) * sizeof(unsigned long long), L->stream));
-    const int grid = grid_for((uint64_t)L->Q, kBinThreads, 1024);
-    bin_stats_kernel<<<grid, kBinThreads, 0, L->stream>>>(L->d_areas, L->Q, d_gbin, n_bins, L->d_stats);
-    HMC_HIP(hipGetLastError());
-    return HMC_OK;
+    return launch_bins(L->d_areas, L->Q, d_gbin, n_bins, L->d_stats, L->stream);
 }
 
 }  // namespace hmc
