@@ -28,7 +28,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
+        # ORACLE_LIB: another build of this library (the sanitizer build)
+        path = os.environ.get("ORACLE_LIB") or _build.ensure_built()
         L = C.CDLL(path)
         P = C.POINTER
         u32p, i32p, i64p, f64p = P(C.c_uint32), P(C.c_int32), P(C.c_int64), P(C.c_double)

@@ -18,14 +18,23 @@ def sources():
     )
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-Wall",
-           "-o", LIB + ".tmp"] + sources() + ["-lm"]
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
+    """Compile the oracle; with sanitize=True an AddressSanitizer and
+    UndefinedBehaviorSanitizer build (load it with gcc's libasan preloaded)
+    into `out` instead of the default library."""
+    lib = out or LIB
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-fPIC", "-shared", "-fopenmp", "-std=c11", "-Wall",
+                           "-o", lib + ".tmp"] + sources() + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 def ensure_built() -> str:

@@ -126,9 +126,11 @@ def lib():
     """The loaded libhmc.so; raises if it has not been built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"libhmc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
-        L = C.CDLL(LIB_PATH)
+        # HMC_LIBRARY: another build of this same library (e.g. the host-sanitizer build)
+        path = os.environ.get("HMC_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError(f"libhmc.so is not built ({path}); run __graft_entry__.build()")
+        L = C.CDLL(path)
         for name, res, args in _SIGS:
             f = getattr(L, name)
             f.restype = res

@@ -23,15 +23,26 @@ def headers():
     return hs + [os.path.join(ROOT, "include", "hmc.h")]
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer (the device code is
+# built as usual); load such a build with clang's ASan runtime preloaded.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize_host: bool = False, out: str = None) -> str:
+    """Compile every HIP source for gfx950 and link libhmc.so (or `out`)."""
+    lib = out or LIB
+    objdir = os.path.dirname(lib) if out else CSRC
     objs = []
     procs = []
     for src in sources():
-        obj = os.path.join(CSRC, os.path.basename(src)[:-4] + ".o")
+        obj = os.path.join(objdir, os.path.basename(src)[:-4] + ".o")
         cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-c",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-command-line-argument",
                "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", obj, src]
+        if sanitize_host:
+            cmd[1:1] = HOST_SANITIZE
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
@@ -43,14 +54,14 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for p, s in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {s}")
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 def is_stale() -> bool:
