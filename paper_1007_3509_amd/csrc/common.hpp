@@ -238,6 +238,12 @@ struct hmc_ensemble_s {
     uint32_t ntiles = 0;
     void* d_lats = nullptr;             // one descriptor per member
     size_t lats_bytes = 0;
+    // pinned host staging of the descriptors, two slots used in turn; the
+    // event after each upload says when its slot may be rewritten
+    void* h_stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_used[2] = {false, false};
+    int stage_slot = 0;
     uint32_t grid = 0;
     std::map<int32_t, hipGraphExec_t> graphs;   // captured launch sequences by n_mcs
     uint32_t graph_launches = 0;

@@ -999,6 +999,10 @@ hmc_status hmc_ensemble_free(hmc_ensemble* E) {
     for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
     dev_free(E->d_tiles, E->tiles_bytes);
     dev_free(E->d_lats, E->lats_bytes);
+    for (int i = 0; i < 2; ++i) {
+        if (E->h_stage[i]) (void)hipHostFree(E->h_stage[i]);
+        if (E->stage_ev[i]) (void)hipEventDestroy(E->stage_ev[i]);
+    }
     (void)hipEventDestroy(E->ev);
     (void)hipStreamDestroy(E->stream);
     delete E;

@@ -1072,8 +1072,20 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         h[i].cur = (uint32_t)L->cur;
         h[i].t_base = (uint32_t)L->mcs;
     }
-    HMC_HIP(hipMemcpyAsync(E->d_lats, h.data(), E->lats_bytes, hipMemcpyHostToDevice, E->stream));
-    HMC_HIP(hipStreamSynchronize(E->stream));
+    // Upload from pinned staging, two slots in turn: the host waits only for
+    // the upload made two calls ago from the same slot (long finished in a
+    // steady loop), never for the replay itself.
+    const int slot = E->stage_slot;
+    if (!E->h_stage[slot]) {
+        HMC_HIP(hipHostMalloc(&E->h_stage[slot], E->lats_bytes, hipHostMallocDefault));
+        HMC_HIP(hipEventCreateWithFlags(&E->stage_ev[slot], hipEventDisableTiming));
+    }
+    if (E->stage_used[slot]) HMC_HIP(hipEventSynchronize(E->stage_ev[slot]));
+    std::memcpy(E->h_stage[slot], h.data(), E->lats_bytes);
+    HMC_HIP(hipMemcpyAsync(E->d_lats, E->h_stage[slot], E->lats_bytes, hipMemcpyHostToDevice, E->stream));
+    HMC_HIP(hipEventRecord(E->stage_ev[slot], E->stream));
+    E->stage_used[slot] = true;
+    E->stage_slot = slot ^ 1;
 
     auto it = E->graphs.find(n_mcs);
     if (it == E->graphs.end()) {
