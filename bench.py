@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--workload", default="schmid_3d_256", choices=sorted(WORKLOADS) + list(SPECIAL))
     ap.add_argument("--mcs", type=int, default=0, help="override MC steps per job")
     ap.add_argument("--tiling", default="", help="tx,ty,tz,k (default: library choice)")
+    ap.add_argument("--kernel", default="auto", choices=("auto", "generic"),
+                    help="sweep kernel: auto (the compiled-tile kernel where it applies) or the general one")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -205,6 +207,8 @@ def main():
         lat.set_pair_energy(gpu_table)
     if args.tiling:
         lat.set_tiling(*[int(v) for v in args.tiling.split(",")])
+    if args.kernel == "generic":
+        hmc.hmc_set_sweep_kernel(lat.h, hmc.HMC_KERNEL_GENERIC)
     start = lat.spins()
     rule = w.extra.get("field_rule")
     field = None

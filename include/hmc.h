@@ -251,6 +251,16 @@ hmc_status hmc_set_mcs(hmc_lattice *L, uint64_t mcs);
 hmc_status hmc_set_tiling(hmc_lattice *L, int32_t tx, int32_t ty, int32_t tz, int32_t mcs_per_launch);
 hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
 
+/* Which sweep kernel runs the Red/Black passes (Sec. 4).  HMC_KERNEL_AUTO
+ * (the default): the six-neighbour 16-bit model with neighbour trials, one
+ * bond energy and grain energies runs a kernel compiled for its tile
+ * (64x16x16, 32x32x16, 32x16x16, 16x16x16 or 64x16x8; one or two colour
+ * passes per launch, lattice x side a multiple of 4), everything else the
+ * general tile kernel; HMC_KERNEL_GENERIC: always the general kernel.  The
+ * spins do not depend on the choice.  Errors: INVAL. */
+enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1 };
+hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);
+
 /* Kernel timing with HIP events recorded around every sweep launch on the
  * lattice's stream.  profile_read synchronises, returns the summed kernel
  * time, the number of launches and the site updates they performed since

@@ -153,6 +153,25 @@ struct Tiling {
 };
 inline int launch_passes(const Tiling& t, int C) { return t.k > 0 ? t.k * C : -t.k; }
 
+// Arguments of the six-neighbour 16-bit sweep kernel with compile-time tile
+// geometry (sweep_vn6.hip); one or two colour passes per launch.
+struct Vn6Args {
+    const int16_t* src;
+    int16_t* dst;
+    const int32_t* B;
+    const uint32_t* T;            // threshold table (rows x TW)
+    const uint32_t* Tb;           // per-bucket (lower, upper) bounds of T
+    uint32_t Lx, Ly, Lz, ntx, nty;
+    uint32_t t0, c0, npass;       // MC step and colour of the first pass; passes (1 or 2)
+    uint32_t k0, k1;              // Philox key
+    int32_t J_fx, Q, dn_lo, TW, R, nb, nbound;
+    uint32_t bw, m_bw, xcd_group;
+    unsigned long long* trials;   // profiling: Philox draws, or null
+};
+// The specialised kernel for tile t (and its dynamic LDS size), or false
+// when t is not one of its compiled tiles or does not fit the LDS.
+bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes);
+
 // --------------------------------------------------------------- lattice
 
 }  // namespace hmc
@@ -189,6 +208,7 @@ struct hmc_lattice_s {
 
     hmc::Tiling tiling;
     bool tiling_explicit = false;
+    int32_t sweep_kernel = 0;               // HMC_KERNEL_AUTO or HMC_KERNEL_GENERIC
 
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

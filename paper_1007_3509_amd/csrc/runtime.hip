@@ -330,7 +330,7 @@ using namespace hmc;
 
 extern "C" {
 
-int32_t hmc_abi_version(void) { return 5; }
+int32_t hmc_abi_version(void) { return 6; }
 
 const char* hmc_last_error(void) { return g_error.c_str(); }
 
@@ -668,6 +668,14 @@ hmc_status hmc_set_tiling(hmc_lattice* L, int32_t tx, int32_t ty, int32_t tz, in
     HMC_TRY(choose_tiling(L, t, true));
     L->tiling = t;
     L->tiling_explicit = true;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_sweep_kernel(hmc_lattice* L, int32_t which) {
+    g_error.clear();
+    if (!L) return fail(HMC_E_INVAL, "lattice is NULL");
+    if (which != HMC_KERNEL_AUTO && which != HMC_KERNEL_GENERIC) return fail(HMC_E_INVAL, "unknown sweep kernel");
+    L->sweep_kernel = which;
     return HMC_OK;
 }
 

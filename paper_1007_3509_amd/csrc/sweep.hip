@@ -648,12 +648,11 @@ Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tili
     o.BY = (uint32_t)(t.ty + 2 * passes);
     o.BZ = ndim == 3 ? (uint32_t)(t.tz + 2 * passes) : 1u;
     const size_t elems = (size_t)o.BX * o.BY * o.BZ;
-    size_t qcap;
-    switch (nbr) {
-    case HMC_VN4: case HMC_VN6: qcap = elems / 2 + 1; break;
-    case HMC_MOORE8: qcap = elems / 4 + 1; break;
-    default: qcap = elems / 8 + 1; break;
-    }
+    // The queue holds at most the colour class of the first (largest) pass
+    // region, which is one ring inside the box (x from the padded edge):
+    // every side of it is even, so the class is exactly 1/C of the region.
+    const size_t W0x = o.BX - 2 * (1 + (o.HX - o.H)), W0y = o.BY - 2, W0z = ndim == 3 ? o.BZ - 2 : 1;
+    const size_t qcap = W0x * W0y * W0z / (size_t)nbr_info(nbr).C + 1;
     o.box_off = kHeaderBytes;
     o.queue_off = o.box_off + (elems * spin_bytes + 15) / 16 * 16;
     o.coord_off = o.queue_off + (qcap * 4 + 15) / 16 * 16;
@@ -940,20 +939,45 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         chunks.back() = pl / 2;
         chunks.push_back(pl - pl / 2);
     }
+    // The six-neighbour 16-bit model with neighbour trials, one bond energy
+    // and grain energies has a kernel of its own for its common tiles.
+    const void* vfn = nullptr;
+    size_t vbytes = 0;
+    const bool vn6 = L->sweep_kernel == HMC_KERNEL_AUTO && L->desc.nbr == HMC_VN6 && L->desc.spin == HMC_I16 &&
+                     L->desc.proposal == HMC_PROP_NEIGHBOUR && !L->pair && !L->field && P <= 2 && vec_ok(L, t) &&
+                     vn6_kernel_for(t, L->Q, &vfn, &vbytes);
+    Vn6Args va{};
+    if (vn6) {
+        va.B = a.B; va.T = a.T; va.Tb = a.Tb;
+        va.Lx = a.Lx; va.Ly = a.Ly; va.Lz = a.Lz; va.ntx = a.ntx; va.nty = a.nty;
+        va.k0 = a.k0; va.k1 = a.k1;
+        va.J_fx = a.J_fx; va.Q = a.Q; va.dn_lo = a.dn_lo; va.TW = a.TW; va.R = a.R; va.nb = a.nb;
+        va.nbound = a.nbound; va.bw = a.bw; va.m_bw = a.m_bw; va.xcd_group = xcd_group;
+        va.trials = a.trials;
+    }
     int64_t gp0 = 0;   // passes done in this call
     for (const int passes : chunks) {
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
-        const void* kfn = kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair, L->field);
+        const void* kfn = vn6 ? vfn : kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair,
+                                                 L->field);
+        const size_t lds = vn6 ? vbytes : lay.bytes;
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
         a.fsrc = L->d_field[L->cur];
         a.fdst = L->d_field[L->cur ^ 1];
         a.t0 = (uint32_t)(L->mcs + (uint64_t)(gp0 / L->C));
         a.c0 = (uint32_t)(gp0 % L->C);
+        va.src = static_cast<const int16_t*>(a.src);
+        va.dst = static_cast<int16_t*>(a.dst);
+        va.t0 = a.t0;
+        va.c0 = a.c0;
+        va.npass = (uint32_t)passes;
         uint32_t xg = xcd_group;
-        void* args[] = {&a, &g, &xg};
+        void* gargs[] = {&a, &g, &xg};
+        void* vargs[] = {&va};
+        void** args = vn6 ? vargs : gargs;
         if (L->profiling) {
             // Events bound to the dispatch itself: they time the kernel, not
             // the queue around it.
@@ -964,12 +988,12 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
                 L->events.emplace_back(e0, e1);
             }
             const auto& ev = L->events[L->events_used++];
-            HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream, ev.first,
+            HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lds, L->stream, ev.first,
                                        ev.second, 0));
             L->prof_launches += 1;
             L->prof_su += (int64_t)passes * L->N / L->C;
         } else {
-            HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lay.bytes, L->stream));
+            HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lds, L->stream));
         }
         L->cur ^= 1;
         gp0 += passes;
