@@ -75,7 +75,8 @@ def measured_profile(workload, tiling, kernel="sweep_tile_kernel"):
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "sweep.hip")
+    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc",
+                       "sweep_vn6.hip" if kernel == "vn6_tile_kernel" else "sweep.hip")
     if not os.path.exists(path):
         return {}
     keys = ("traffic_bytes_per_launch", "valu_wave_instructions_per_launch", "kernel_source_sha256", "tiling")
@@ -259,7 +260,8 @@ def main():
     su_per_launch = su / max(launches, 1)
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
     tiling = lat.tiling()
-    prof = measured_profile(w.name, tiling)
+    kname = "vn6_tile_kernel" if hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED else "sweep_tile_kernel"
+    prof = measured_profile(w.name, tiling, kernel=kname)
     traffic = prof.get("traffic_bytes_per_launch")
     valu = prof.get("valu_wave_instructions_per_launch")
 
@@ -295,7 +297,7 @@ def main():
             "frac": achieved / PEAK_HBM_GBPS,
             "traffic": traffic,
             "traffic_note": "scaled FETCH_SIZE+WRITE_SIZE bytes per launch from profiles/ (null if the kernel changed)",
-            "kernel": "sweep_tile_kernel",
+            "kernel": kname,
             "avg_launch_us": avg_launch_s * 1e6,
             "launch_timing": "HIP events bound to each sweep dispatch, replay of the timed steps",
             "launches": launches,

@@ -258,8 +258,11 @@ hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
  * passes per launch, lattice x side a multiple of 4), everything else the
  * general tile kernel; HMC_KERNEL_GENERIC: always the general kernel.  The
  * spins do not depend on the choice.  Errors: INVAL. */
-enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1 };
+enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1, HMC_KERNEL_COMPILED = 2 };
 hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);
+/* The kernel the next full sweep launch of L will run: HMC_KERNEL_COMPILED
+ * (the compiled-tile kernel) or HMC_KERNEL_GENERIC.  Errors: INVAL. */
+hmc_status hmc_get_sweep_kernel(const hmc_lattice *L, int32_t *which);
 
 /* Kernel timing with HIP events recorded around every sweep launch on the
  * lattice's stream.  profile_read synchronises, returns the summed kernel

@@ -74,6 +74,7 @@ _SIGS = [
     ("hmc_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("hmc_get_tiling", C.c_int32, [C.c_void_p, C.c_void_p]),
     ("hmc_set_sweep_kernel", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("hmc_get_sweep_kernel", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("hmc_profile", C.c_int32, [C.c_void_p, C.c_int32]),
     ("hmc_profile_read", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]),
@@ -305,11 +306,17 @@ def hmc_set_tiling(h, tx=0, ty=0, tz=0, mcs_per_launch=0):
     _check(lib().hmc_set_tiling(h, int(tx), int(ty), int(tz), int(mcs_per_launch)))
 
 
-HMC_KERNEL_AUTO, HMC_KERNEL_GENERIC = 0, 1
+HMC_KERNEL_AUTO, HMC_KERNEL_GENERIC, HMC_KERNEL_COMPILED = 0, 1, 2
 
 
 def hmc_set_sweep_kernel(h, which):
     _check(lib().hmc_set_sweep_kernel(h, int(which)))
+
+
+def hmc_get_sweep_kernel(h):
+    w = C.c_int32()
+    _check(lib().hmc_get_sweep_kernel(h, C.byref(w)))
+    return int(w.value)
 
 
 def hmc_get_tiling(h):

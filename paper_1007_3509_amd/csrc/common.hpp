@@ -168,8 +168,9 @@ struct Vn6Args {
     uint32_t bw, m_bw, xcd_group;
     unsigned long long* trials;   // profiling: Philox draws, or null
 };
-// The specialised kernel for tile t (and its dynamic LDS size), or false
-// when t is not one of its compiled tiles or does not fit the LDS.
+// The specialised kernel for tile t (and its dynamic LDS size) given Q
+// grains, or false when t is not one of its compiled tiles or does not fit
+// the LDS.
 bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes);
 
 // --------------------------------------------------------------- lattice
@@ -284,6 +285,8 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
 const Tiling* tuned_tiling(const hmc_lattice_desc& d, int32_t Q);
 void record_tuning(const hmc_lattice_desc& d, const Tiling& t, double us_per_mcs);
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request);
+// True when sweeps of L with tiling t run the compiled-tile kernel.
+bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes);
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
 hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas

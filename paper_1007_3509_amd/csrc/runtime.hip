@@ -679,6 +679,17 @@ hmc_status hmc_set_sweep_kernel(hmc_lattice* L, int32_t which) {
     return HMC_OK;
 }
 
+hmc_status hmc_get_sweep_kernel(const hmc_lattice* L, int32_t* which) {
+    g_error.clear();
+    if (!L || !which) return fail(HMC_E_INVAL, "NULL argument");
+    Tiling t = L->tiling;
+    HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
+    const void* fn = nullptr;
+    size_t bytes = 0;
+    *which = compiled_vn6(L, t, &fn, &bytes) ? HMC_KERNEL_COMPILED : HMC_KERNEL_GENERIC;
+    return HMC_OK;
+}
+
 hmc_status hmc_get_tiling(const hmc_lattice* L, int32_t* out4) {
     g_error.clear();
     if (!L || !out4) return fail(HMC_E_INVAL, "NULL argument");

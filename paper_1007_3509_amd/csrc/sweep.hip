@@ -904,6 +904,15 @@ hmc_status settle_borrowed(hmc_lattice* L) {
     return HMC_OK;
 }
 
+// The six-neighbour 16-bit model with neighbour trials, one bond energy and
+// grain energies has a kernel of its own for its common tiles (one or two
+// colour passes per launch).
+bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes) {
+    return L->sweep_kernel == HMC_KERNEL_AUTO && L->desc.nbr == HMC_VN6 && L->desc.spin == HMC_I16 &&
+           L->desc.proposal == HMC_PROP_NEIGHBOUR && !L->pair && !L->field && launch_passes(t, L->C) <= 2 &&
+           vec_ok(L, t) && L->desc.J_fx < (1 << 23) && vn6_kernel_for(t, L->Q, fn, bytes);
+}
+
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
     if (n_mcs == 0) return HMC_OK;
     if (L->pair || L->field) {
@@ -939,13 +948,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         chunks.back() = pl / 2;
         chunks.push_back(pl - pl / 2);
     }
-    // The six-neighbour 16-bit model with neighbour trials, one bond energy
-    // and grain energies has a kernel of its own for its common tiles.
     const void* vfn = nullptr;
     size_t vbytes = 0;
-    const bool vn6 = L->sweep_kernel == HMC_KERNEL_AUTO && L->desc.nbr == HMC_VN6 && L->desc.spin == HMC_I16 &&
-                     L->desc.proposal == HMC_PROP_NEIGHBOUR && !L->pair && !L->field && P <= 2 && vec_ok(L, t) &&
-                     vn6_kernel_for(t, L->Q, &vfn, &vbytes);
+    const bool vn6 = compiled_vn6(L, t, &vfn, &vbytes);
     Vn6Args va{};
     if (vn6) {
         va.B = a.B; va.T = a.T; va.Tb = a.Tb;
