@@ -165,7 +165,9 @@ struct Vn6Args {
     uint32_t t0, c0, npass;       // MC step and colour of the first pass; passes (1 or 2)
     uint32_t k0, k1;              // Philox key
     int32_t J_fx, Q, dn_lo, TW, R, nb, nbound;
-    uint32_t bw, m_bw, xcd_group;
+    uint32_t bw, m_bw;
+    uint32_t ntiles;              // tiles of the lattice; workgroups walk them in turn
+    uint32_t xcd_blocks;          // 1: each XCD's workgroups take one contiguous block of tiles
     unsigned long long* trials;   // profiling: Philox draws, or null
 };
 // The specialised kernel for tile t (and its dynamic LDS size) given Q

@@ -957,7 +957,8 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         va.Lx = a.Lx; va.Ly = a.Ly; va.Lz = a.Lz; va.ntx = a.ntx; va.nty = a.nty;
         va.k0 = a.k0; va.k1 = a.k1;
         va.J_fx = a.J_fx; va.Q = a.Q; va.dn_lo = a.dn_lo; va.TW = a.TW; va.R = a.R; va.nb = a.nb;
-        va.nbound = a.nbound; va.bw = a.bw; va.m_bw = a.m_bw; va.xcd_group = xcd_group;
+        va.nbound = a.nbound; va.bw = a.bw; va.m_bw = a.m_bw;
+        va.ntiles = ntiles;
         va.trials = a.trials;
     }
     int64_t gp0 = 0;   // passes done in this call
@@ -983,6 +984,10 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         void* gargs[] = {&a, &g, &xg};
         void* vargs[] = {&va};
         void** args = vn6 ? vargs : gargs;
+        // the compiled-tile kernel is persistent: one workgroup per CU walks
+        // its share of the tiles, prefetching the next box during each tile
+        const uint32_t grid = vn6 ? std::min<uint32_t>(ntiles, (uint32_t)device_cus()) : ntiles;
+        va.xcd_blocks = (vn6 && grid % 8 == 0) ? 1u : 0u;
         if (L->profiling) {
             // Events bound to the dispatch itself: they time the kernel, not
             // the queue around it.
@@ -993,12 +998,12 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
                 L->events.emplace_back(e0, e1);
             }
             const auto& ev = L->events[L->events_used++];
-            HMC_HIP(hipExtLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lds, L->stream, ev.first,
+            HMC_HIP(hipExtLaunchKernel(kfn, dim3(grid), dim3(kThreads), args, lds, L->stream, ev.first,
                                        ev.second, 0));
             L->prof_launches += 1;
             L->prof_su += (int64_t)passes * L->N / L->C;
         } else {
-            HMC_HIP(hipLaunchKernel(kfn, dim3(ntiles), dim3(kThreads), args, lds, L->stream));
+            HMC_HIP(hipLaunchKernel(kfn, dim3(grid), dim3(kThreads), args, lds, L->stream));
         }
         L->cur ^= 1;
         gp0 += passes;

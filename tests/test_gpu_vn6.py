@@ -3,8 +3,10 @@ against the general tile kernel and the oracle, element by element (Sec. 3
 trials, Sec. 4 Red/Black passes).
 
 * every compiled tile, two and one colour passes per launch, grains in LDS
-  (Q <= 4096) and in global memory, on a lattice of several tiles along
-  every axis: spins equal to the oracle's and to the general kernel's;
+  (Q <= 4096) and in global memory (also with an energy spread beyond
+  2^16), on lattices of several tiles along every axis, with more tiles than
+  workgroups (each walks several, prefetching the next): spins equal to the
+  oracle's and to the general kernel's;
 * both kernels queue the same trials (profiling counter);
 * a caller's buffer (launch counts of either parity, so single-pass
   launches starting on either colour) and values outside [0, Q) that stay
@@ -59,6 +61,36 @@ def test_compiled_tiles_equal_general_kernel_and_oracle(tiling, Q):
     assert np.array_equal(got, want), f"{int(np.sum(got != want))} sites differ from the oracle"
     assert np.array_equal(gen, want)
     assert tr_a == tr_g and tr_a > 0
+
+
+@pytest.mark.parametrize("tiling", [(64, 16, 16, 1), (32, 16, 16, -1)])
+def test_wide_energy_spread_reads_grains_from_global_memory(tiling):
+    """Grain energies spread over more than 2^16 fixed-point units cannot be
+    staged as 16-bit offsets; the kernel reads them from global memory."""
+    dims, Q, kT, seed = (128, 64, 48), 6000, 1.5, 13
+    B = synth.quantise(np.random.default_rng(2).uniform(-1.2, 1.2, Q))
+    assert int(B.max()) - int(B.min()) >= 65536
+    say(f"[gpu] vn6 wide spread tiling={tiling}")
+    start, got, tr_a = _run(dims, Q, B, kT, [5], seed, tiling, hmc.HMC_KERNEL_AUTO)
+    _, gen, tr_g = _run(dims, Q, B, kT, [5], seed, tiling, hmc.HMC_KERNEL_GENERIC)
+    want = oracle.sweep(start, hmc.HMC_VN6, dims, B, kT, 5, seed, threads=8)
+    assert np.array_equal(got, want) and np.array_equal(gen, want)
+    assert tr_a == tr_g
+
+
+@pytest.mark.parametrize("dims,tiling", [((128, 128, 128), (16, 16, 16, 1)), ((144, 128, 128), (16, 16, 16, 1)),
+                                         ((144, 128, 128), (16, 16, 16, -1))])
+def test_workgroups_walk_several_tiles(dims, tiling):
+    """More tiles than workgroups (one per CU): each workgroup walks several
+    tiles, prefetching the next box; 576 tiles do not split evenly."""
+    Q, kT, seed = 6000, 0.6, 17
+    B = synth.quantise(0.15 * (0.27 + 0.23 * np.random.default_rng(4).random(Q)))
+    say(f"[gpu] vn6 several tiles per workgroup dims={dims} tiling={tiling}")
+    start, got, tr_a = _run(dims, Q, B, kT, [2, 1], seed, tiling, hmc.HMC_KERNEL_AUTO)
+    _, gen, tr_g = _run(dims, Q, B, kT, [2, 1], seed, tiling, hmc.HMC_KERNEL_GENERIC)
+    want = oracle.sweep(start, hmc.HMC_VN6, dims, B, kT, 3, seed, threads=8)
+    assert np.array_equal(got, want), f"{int(np.sum(got != want))} sites differ from the oracle"
+    assert np.array_equal(gen, want) and tr_a == tr_g
 
 
 def test_wrapped_buffer_parities_and_inert_values():
