@@ -77,6 +77,10 @@ enum { kGrainGlobal = 0, kGrainLds32 = 1 };
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS
 // operations, not for its global loads, so a prefetch of the next tile stays
 // in flight across the passes (all communication inside a pass is in LDS).
+// s_waitcnt operand that waits for vector memory operations only (vmcnt 0,
+// export and LDS/scalar counters left at their maxima)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -149,7 +153,8 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
             const uint32_t e = tid + (uint32_t)j * kVThreads;
             const uint32_t ec = e < (uint32_t)G::NWORDS ? e : 0u;
             const uint32_t r = ec / NW, u4 = ec - r * NW;
-            pre[j] = *reinterpret_cast<const uint64_t*>(a.src + gxs(set)[4 * u4] + rows(set)[r]);
+            const uint32_t site = gxs(set)[4 * u4] + rows(set)[r];   // < 2^32 sites
+            pre[j] = *reinterpret_cast<const uint64_t*>(a.src + site);
         }
     };
     auto commit = [&]() __attribute__((always_inline)) {
@@ -175,6 +180,7 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
         prefetch(0);
         commit();
     }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // every lane's words, committed or not, have landed
     lds_barrier();
 
     unsigned long long drawn = 0;
@@ -224,11 +230,18 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
                     const uint32_t k = (c + v + w + org) & 1u;   // first field of colour c
                     // the one x neighbour outside the word that a colour-c field
                     // has: the site before the word (k = 0) or after it (k = 1)
-                    const uint64_t e = (uint16_t)box[k ? 4 * wi + 4 : 4 * wi - 1];
-                    const uint64_t x = (S ^ ((S << 16) | e)) | (S ^ ((S >> 16) | (e << 48))) | (S ^ U) | (S ^ D) |
-                                       (S ^ F) | (S ^ K);
-                    const uint32_t fa = __builtin_amdgcn_ubfe((uint32_t)x, 16 * k, 16);
-                    const uint32_t fb = __builtin_amdgcn_ubfe((uint32_t)(x >> 32), 16 * k, 16);
+                    const uint32_t e = (uint16_t)box[k ? 4 * wi + 4 : 4 * wi - 1];
+                    // the word shifted by one site towards +x and towards -x, as
+                    // 32-bit halves (funnel shifts instead of 64-bit shifts)
+                    const uint32_t lo = (uint32_t)S, hi = (uint32_t)(S >> 32);
+                    const uint32_t mid = __builtin_amdgcn_alignbit(hi, lo, 16);   // sites 1, 2
+                    const uint32_t xl = (lo ^ ((lo << 16) | e)) | (lo ^ mid) | (lo ^ (uint32_t)U) |
+                                        (lo ^ (uint32_t)D) | (lo ^ (uint32_t)F) | (lo ^ (uint32_t)K);
+                    const uint32_t xh = (hi ^ mid) | (hi ^ __builtin_amdgcn_alignbit(e, hi, 16)) |
+                                        (hi ^ (uint32_t)(U >> 32)) | (hi ^ (uint32_t)(D >> 32)) |
+                                        (hi ^ (uint32_t)(F >> 32)) | (hi ^ (uint32_t)(K >> 32));
+                    const uint32_t fa = __builtin_amdgcn_ubfe(xl, 16 * k, 16);
+                    const uint32_t fb = __builtin_amdgcn_ubfe(xh, 16 * k, 16);
                     pa = fa != 0 && ((okmask >> k) & 1u);
                     pb = fb != 0 && ((okmask >> (k + 2)) & 1u);
                     const uint32_t ia = 4 * wi + k;
@@ -279,13 +292,24 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
                 const uint32_t kk = __umulhi(rn.r0, 6u);
                 const int32_t qn = box[(int32_t)idx + noff[kk]];
                 if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
-                int cq = 0, cn = 0;
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    cq += (nb[j] == q);
-                    cn += (nb[j] == qn);
-                }
-                const int32_t dn = cq - cn;
+                // The neighbours two to a register (16-bit halves); per half,
+                // min(x ^ y, 1) is 1 where two spins differ, so one packed
+                // minimum tests two neighbours.
+                const uint32_t p0 = __builtin_amdgcn_perm((uint32_t)nb[1], (uint32_t)nb[0], 0x05040100u);
+                const uint32_t p1 = __builtin_amdgcn_perm((uint32_t)nb[3], (uint32_t)nb[2], 0x05040100u);
+                const uint32_t p2 = __builtin_amdgcn_perm((uint32_t)nb[5], (uint32_t)nb[4], 0x05040100u);
+                const uint32_t qq = __builtin_amdgcn_perm((uint32_t)q, (uint32_t)q, 0x05040100u);
+                const uint32_t nn = __builtin_amdgcn_perm((uint32_t)qn, (uint32_t)qn, 0x05040100u);
+                auto ne = [](uint32_t x) __attribute__((always_inline)) -> uint32_t {
+                    uint32_t r;
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(x), "s"(0x00010001u));
+                    return r;
+                };
+                const uint32_t uq = ne(p0 ^ qq) + ne(p1 ^ qq) + ne(p2 ^ qq);   // per half <= 3
+                const uint32_t un = ne(p0 ^ nn) + ne(p1 ^ nn) + ne(p2 ^ nn);
+                const uint32_t D = un + 0x00030003u - uq;                          // per half in [0, 6]
+                // (likes of q) - (likes of qn) = (unlikes of qn) - (unlikes of q)
+                const int32_t dn = (int32_t)((D & 0xFFFFu) + (D >> 16)) - 6;
                 const int32_t dB = energy(qn) - bq;
                 const int32_t d = __mul24(a.J_fx, dn) + dB;   // J_fx < 2^23 (checked on the host)
                 bool accept = d <= 0;
@@ -317,6 +341,10 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
             else pass(std::integral_constant<int, 2>{}, c, t, p & 1u);
         }
 
+        // The next box has long arrived: wait for it here, before the stores,
+        // so that nothing later (the commit, the next prefetch into the same
+        // registers) has to wait for the stores themselves to complete.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         // The tile back to global memory, 8-byte words.
         constexpr int TW4 = TX / 4;
         const uint32_t gx0 = (uint32_t)(x0 + HX);
