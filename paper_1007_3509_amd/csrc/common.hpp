@@ -83,6 +83,36 @@ __device__ __forceinline__ Philox2 philox_r01(uint32_t c0, uint32_t c1, uint32_t
     return Philox2{o[0], o[1]};
 }
 
+// ------------------------------------------------------- like neighbours
+
+// (neighbours equal to q) - (neighbours equal to qn) over M 16-bit spin
+// values (M even).  The values go two to a register as 16-bit halves; per
+// half, min(x ^ y, 1) is 1 where two spins differ, so one packed minimum
+// tests two neighbours, and the difference of the likes is the difference of
+// the unlikes taken the other way round.
+template <int M>
+__device__ __forceinline__ int32_t like_difference16(const int32_t* nb, int32_t q, int32_t qn) {
+    static_assert(M % 2 == 0 && M <= 64, "pairs of neighbours, per-half counts below 2^15");
+    auto pack = [](int32_t hi, int32_t lo) __attribute__((always_inline)) {
+        return __builtin_amdgcn_perm((uint32_t)hi, (uint32_t)lo, 0x05040100u);
+    };
+    auto ne = [](uint32_t x) __attribute__((always_inline)) -> uint32_t {
+        uint32_t r;
+        asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(x), "s"(0x00010001u));
+        return r;
+    };
+    const uint32_t qq = pack(q, q), nn = pack(qn, qn);
+    uint32_t uq = 0, un = 0;
+#pragma unroll
+    for (int k = 0; k < M; k += 2) {
+        const uint32_t p = pack(nb[k + 1], nb[k]);
+        uq += ne(p ^ qq);
+        un += ne(p ^ nn);
+    }
+    const uint32_t D = un + (uint32_t)(M / 2) * 0x00010001u - uq;   // per half in [0, M]
+    return (int32_t)((D & 0xFFFFu) + (D >> 16)) - M;
+}
+
 // --------------------------------------------------------------- geometry
 
 struct NbrInfo {

@@ -339,13 +339,18 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                 if (d <= 0 || r.r1 < a.Tg[min(d, a.Dmax)]) box[idx] = (Spin)qn;
                 return;
             }
-            int cq = 0, cn = 0;
+            int32_t dn;
+            if constexpr (sizeof(Spin) == 2 && M % 2 == 0) {
+                dn = like_difference16<M>(nb, q, qn);
+            } else {
+                int cq = 0, cn = 0;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                cq += (nb[k] == q);
-                cn += (nb[k] == qn);
+                for (int k = 0; k < M; ++k) {
+                    cq += (nb[k] == q);
+                    cn += (nb[k] == qn);
+                }
+                dn = cq - cn;
             }
-            const int32_t dn = cq - cn;
             const int32_t dB = Bq[qn] - bq;
             if constexpr (kField) {
                 // per-site field: dE gains e_new - e_i; threshold per d
@@ -400,15 +405,21 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     const uint32_t row = __umul24(g.BX, v + __umul24(g.BY, w));
                     const uint32_t u0 = 4 * sg;
                     const uint64_t S = *reinterpret_cast<const uint64_t*>(box + row + u0);
-                    uint64_t x;
+                    uint64_t x;   // per 16-bit field: nonzero where a neighbour differs
                     if (a.uniform) {
                         x = ~0ull;
                     } else {
                         const uint64_t Up = *reinterpret_cast<const uint64_t*>(box + row - g.BX + u0);
                         const uint64_t Dn = *reinterpret_cast<const uint64_t*>(box + row + g.BX + u0);
-                        const uint64_t sL = (uint16_t)box[row + (u0 > 0 ? u0 - 1 : 0)];
-                        const uint64_t sR = (uint16_t)box[row + (u0 + 4 < g.BX ? u0 + 4 : g.BX - 1)];
-                        x = (S ^ ((S << 16) | sL)) | (S ^ ((S >> 16) | (sR << 48))) | (S ^ Up) | (S ^ Dn);
+                        const uint32_t sL = (uint16_t)box[row + (u0 > 0 ? u0 - 1 : 0)];
+                        const uint32_t sR = (uint16_t)box[row + (u0 + 4 < g.BX ? u0 + 4 : g.BX - 1)];
+                        // the word shifted one site each way, as 32-bit halves
+                        // (funnel shifts instead of 64-bit shifts)
+                        const uint32_t lo = (uint32_t)S, hi = (uint32_t)(S >> 32);
+                        const uint32_t mid = __builtin_amdgcn_alignbit(hi, lo, 16);   // sites 1, 2
+                        const uint32_t xl = (lo ^ ((lo << 16) | sL)) | (lo ^ mid);
+                        const uint32_t xh = (hi ^ mid) | (hi ^ __builtin_amdgcn_alignbit(sR, hi, 16));
+                        x = (((uint64_t)xh << 32) | xl) | (S ^ Up) | (S ^ Dn);
                         if (D == 3) {
                             const uint64_t Fr = *reinterpret_cast<const uint64_t*>(box + row - plane + u0);
                             const uint64_t Bk = *reinterpret_cast<const uint64_t*>(box + row + plane + u0);
@@ -417,8 +428,8 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     }
                     const uint32_t k = (c ^ (v + w + pbase)) & 1u;   // first colour-c field
                     const uint32_t ua = u0 + k, ub = u0 + k + 2;
-                    pa[j] = ua >= lox && ua < g.BX - lox && ((x >> (16 * k)) & 0xFFFFull) != 0;
-                    pb[j] = ub >= lox && ub < g.BX - lox && ((x >> (16 * (k + 2))) & 0xFFFFull) != 0;
+                    pa[j] = ua >= lox && ua < g.BX - lox && __builtin_amdgcn_ubfe((uint32_t)x, 16 * k, 16) != 0;
+                    pb[j] = ub >= lox && ub < g.BX - lox && __builtin_amdgcn_ubfe((uint32_t)(x >> 32), 16 * k, 16) != 0;
                     qa[j] = ua | (v << 10) | (w << 20);
                     qb[j] = ub | (v << 10) | (w << 20);
                 }

@@ -292,24 +292,7 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
                 const uint32_t kk = __umulhi(rn.r0, 6u);
                 const int32_t qn = box[(int32_t)idx + noff[kk]];
                 if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
-                // The neighbours two to a register (16-bit halves); per half,
-                // min(x ^ y, 1) is 1 where two spins differ, so one packed
-                // minimum tests two neighbours.
-                const uint32_t p0 = __builtin_amdgcn_perm((uint32_t)nb[1], (uint32_t)nb[0], 0x05040100u);
-                const uint32_t p1 = __builtin_amdgcn_perm((uint32_t)nb[3], (uint32_t)nb[2], 0x05040100u);
-                const uint32_t p2 = __builtin_amdgcn_perm((uint32_t)nb[5], (uint32_t)nb[4], 0x05040100u);
-                const uint32_t qq = __builtin_amdgcn_perm((uint32_t)q, (uint32_t)q, 0x05040100u);
-                const uint32_t nn = __builtin_amdgcn_perm((uint32_t)qn, (uint32_t)qn, 0x05040100u);
-                auto ne = [](uint32_t x) __attribute__((always_inline)) -> uint32_t {
-                    uint32_t r;
-                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(x), "s"(0x00010001u));
-                    return r;
-                };
-                const uint32_t uq = ne(p0 ^ qq) + ne(p1 ^ qq) + ne(p2 ^ qq);   // per half <= 3
-                const uint32_t un = ne(p0 ^ nn) + ne(p1 ^ nn) + ne(p2 ^ nn);
-                const uint32_t D = un + 0x00030003u - uq;                          // per half in [0, 6]
-                // (likes of q) - (likes of qn) = (unlikes of qn) - (unlikes of q)
-                const int32_t dn = (int32_t)((D & 0xFFFFu) + (D >> 16)) - 6;
+                const int32_t dn = like_difference16<6>(nb, q, qn);
                 const int32_t dB = energy(qn) - bq;
                 const int32_t d = __mul24(a.J_fx, dn) + dB;   // J_fx < 2^23 (checked on the host)
                 bool accept = d <= 0;
