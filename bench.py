@@ -68,15 +68,24 @@ def parse():
     return ap.parse_args()
 
 
+def source_sha(kernel_file):
+    """sha256 of a kernel's source file followed by the header it inlines
+    (random numbers, acceptance helpers): what a profile was taken on."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1007_3509_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (kernel_file, "common.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_profile(workload, tiling, kernel="sweep_tile_kernel"):
     """Per-launch figures of the sweep (or ensemble) kernel from the committed
     rocprofv3 summary (scaled HBM bytes, VALU wave instructions), or {} when
     the kernel source or the tiling changed since they were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc",
-                       "sweep_vn6.hip" if kernel == "vn6_tile_kernel" else "sweep.hip")
     if not os.path.exists(path):
         return {}
     keys = ("traffic_bytes_per_launch", "valu_wave_instructions_per_launch", "kernel_source_sha256", "tiling")
@@ -84,8 +93,8 @@ def measured_profile(workload, tiling, kernel="sweep_tile_kernel"):
     for line in open(path):
         if ":" in line and line.split(":")[0] in keys:
             k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            fields[k.strip()] = (v.split() or [""])[0]
+    sha = source_sha("sweep_vn6.hip" if kernel == "vn6_tile_kernel" else "sweep.hip")
     if fields.get("kernel_source_sha256") != sha or fields.get("tiling") != ",".join(str(v) for v in tiling):
         return {}
     return {k: float(fields[k]) for k in keys[:2] if k in fields}
@@ -457,19 +466,15 @@ def nfold_profile():
     """Per-launch SQ_INSTS_VALU and scaled HBM bytes of the n-fold kernel
     from the committed rocprofv3 summary, or None when the kernel source
     changed since."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "nfold_kernel_nfold_ensemble_128.md")
-    src = os.path.join(ROOT, "paper_1007_3509_amd", "csrc", "nfold.hip")
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+            fields[k.strip()] = (v.split() or [""])[0]
+    if fields.get("kernel_source_sha256") != source_sha("nfold.hip"):
         return None
     return {k: float(fields[k]) for k in ("valu_wave_instructions_per_launch", "traffic_bytes_per_launch")
             if k in fields}

@@ -30,7 +30,7 @@ def test_more_than_one_gpu_is_refused():
 def _fields(path):
     out = {}
     for line in open(path):
-        m = re.match(r"^(\w+): (\S+)\s*$", line)
+        m = re.match(r"^(\w+): (\S+)(\s.*)?$", line)
         if m:
             out[m.group(1)] = m.group(2)
     return out
