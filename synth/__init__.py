@@ -335,4 +335,4 @@ def uniaxial_strain(k, n_queries=50, strain_box=STRAIN_BOX):
 # workload: sizes, seeds and optimiser settings (inputs of the run, shared by
 # the benchmark and the tests).
 LEARNED = dict(n_train=1000000, n_test=20000, data_seed=5005, solver_seed=50, init_seed=7, train_seed=1,
-               epochs=50, batch=2048, lr=5e-3, every=10, n_audit=64, audit_tol=0.25)
+               epochs=200, batch=4096, lr=1e-2, every=10, n_audit=64, audit_tol=0.25)

@@ -147,5 +147,8 @@ def test_learned_3d_256_whole_run_bit_exact_with_error_and_drift():
                   f"({R['n_test']} samples); max texture-fraction drift vs the solver in the loop at "
                   f"{w.n_mcs} steps over 4 seeds {drift:.2e}; {fallbacks} of {4 * n_q} queries fell back; "
                   f"train loss {loss:.3g}")
-    assert med < 0.08 and p95 < 0.25
+    # the training recipe gives median 0.040, p95 0.144 (a capacity floor of
+    # the 9-64-64-1 network: longer runs, other batches and initial weights
+    # stay at p95 0.141-0.147)
+    assert med < 0.05 and p95 < 0.18
     assert drift < 5e-3
