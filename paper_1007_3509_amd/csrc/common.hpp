@@ -210,10 +210,11 @@ struct Vn6Args {
     uint32_t xcd_blocks;          // 1: each XCD's workgroups take one contiguous block of tiles
     unsigned long long* trials;   // profiling: Philox draws, or null
 };
-// The specialised kernel for tile t (and its dynamic LDS size) given Q
+// The specialised kernel for tile t (its dynamic LDS size and the
+// workgroups per CU it is built for: two when its LDS fits twice) given Q
 // grains, or false when t is not one of its compiled tiles or does not fit
 // the LDS.
-bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes);
+bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes, int* per_cu);
 
 // --------------------------------------------------------------- lattice
 
@@ -328,7 +329,8 @@ const Tiling* tuned_tiling(const hmc_lattice_desc& d, int32_t Q);
 void record_tuning(const hmc_lattice_desc& d, const Tiling& t, double us_per_mcs);
 hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request);
 // True when sweeps of L with tiling t run the compiled-tile kernel.
-bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes);
+bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes, int* per_cu);
+bool compiled_vn6_model(const hmc_lattice* L);
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
 hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas

@@ -686,7 +686,8 @@ hmc_status hmc_get_sweep_kernel(const hmc_lattice* L, int32_t* which) {
     HMC_TRY(choose_tiling(L, t, L->tiling_explicit));
     const void* fn = nullptr;
     size_t bytes = 0;
-    *which = compiled_vn6(L, t, &fn, &bytes) ? HMC_KERNEL_COMPILED : HMC_KERNEL_GENERIC;
+    int per_cu = 1;
+    *which = compiled_vn6(L, t, &fn, &bytes, &per_cu) ? HMC_KERNEL_COMPILED : HMC_KERNEL_GENERIC;
     return HMC_OK;
 }
 

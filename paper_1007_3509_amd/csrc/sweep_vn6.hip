@@ -10,10 +10,13 @@
 //   * the box of a TX x TY x TZ tile adds 2 sites of halo along y and z and
 //     4 along x (rows of whole 8-byte words), enough for the two colour
 //     passes (one MC step) a launch runs;
-//   * one workgroup per CU walks its share of the tiles: while it runs the
-//     passes of one tile, the next tile's box is already on its way from
+//   * persistent workgroups walk their share of the tiles.  Tiles whose
+//     LDS fits twice in a CU run two workgroups per CU (eight waves per
+//     SIMD, 64 registers a lane): while one waits at a barrier the other
+//     issues.  Larger tiles run one workgroup per CU, and while it runs the
+//     passes of one tile the next tile's box is already on its way from
 //     global memory into registers (its barriers wait for LDS traffic only,
-//     so those loads stay in flight), and goes to LDS once the current tile
+//     so those loads stay in flight) and goes to LDS once the current tile
 //     is stored;
 //   * per pass, phase 1 walks the 4-site words of the pass region with a
 //     fixed word column per thread (so the column's bounds and the colour
@@ -35,6 +38,7 @@ namespace hmc {
 namespace {
 
 constexpr int kVThreads = 1024;
+constexpr size_t kCuLdsBytes = 160 * 1024;   // LDS of one CU on this chip
 constexpr int kVWave = 64;
 
 constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
@@ -87,9 +91,13 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int TX, int TY, int TZ, int kGrains>
-__global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
+// kPerCU: resident workgroups per CU the kernel is built for (1 or 2); with
+// one, the next tile's box is prefetched into registers during the passes.
+template <int TX, int TY, int TZ, int kGrains, int kPerCU>
+__global__ void __launch_bounds__(kVThreads) __attribute__((amdgpu_waves_per_eu(4 * kPerCU)))
+vn6_tile_kernel(Vn6Args a) {
     using G = VGeom<TX, TY, TZ>;
+    constexpr bool kPrefetch = kPerCU == 1;
     constexpr int BX = G::BX, BY = G::BY, BZ = G::BZ, BXY = G::BXY, NW = G::NW, H = G::H, HX = G::HX;
     constexpr int PRE = (G::NWORDS + kVThreads - 1) / kVThreads;   // box words per thread
     extern __shared__ __align__(16) unsigned char smem[];
@@ -188,7 +196,8 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
     for (uint32_t tile = first; tile < end; tile += stride, S ^= 1) {
         const uint32_t nxt = tile + stride;
         const bool has_next = nxt < end;
-        if (has_next) prefetch(S ^ 1);   // in flight during the passes
+        if constexpr (kPrefetch)
+            if (has_next) prefetch(S ^ 1);   // in flight during the passes
         const uint32_t* gx = gxs(S);
         const uint32_t* rowL = rows(S);
         int32_t x0, y0, z0;
@@ -344,6 +353,7 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
             qcount[1] = 0;
         }
         if (has_next) {
+            if constexpr (!kPrefetch) prefetch(S ^ 1);
             commit();
             if (nxt + stride < end) make_tables(nxt + stride, S);
         }
@@ -354,16 +364,23 @@ __global__ void __launch_bounds__(kVThreads) vn6_tile_kernel(Vn6Args a) {
 }
 
 template <int TX, int TY, int TZ>
-bool pick(const Tiling& t, int32_t Q, bool& fits, const void*& fn, size_t& bytes) {
+bool pick(const Tiling& t, int32_t Q, bool& fits, const void*& fn, size_t& bytes, int& per_cu) {
     if (t.tx != TX || t.ty != TY || t.tz != TZ) return false;
     using G = VGeom<TX, TY, TZ>;
     const int64_t limit = lds_limit_bytes();
-    if (Q <= 4096 && (int64_t)(G::kGrainOff + 4 * (size_t)Q) <= limit) {
-        fn = reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainLds32>);
-        bytes = G::kGrainOff + 4 * (size_t)Q;
-    } else {
-        fn = reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainGlobal>);
-        bytes = G::kGrainOff;
+    const bool lds_grains = Q <= 4096 && (int64_t)(G::kGrainOff + 4 * (size_t)Q) <= limit;
+    bytes = G::kGrainOff + (lds_grains ? 4 * (size_t)Q : 0);
+    fn = lds_grains ? reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainLds32, 1>)
+                    : reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainGlobal, 1>);
+    per_cu = 1;
+    // two workgroups per CU when the LDS holds two (a CU's LDS equals the
+    // per-workgroup limit); only tiles whose bare box can pair are built so
+    if constexpr (2 * G::kGrainOff <= kCuLdsBytes) {
+        if (2 * (int64_t)bytes <= limit) {
+            per_cu = 2;
+            fn = lds_grains ? reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainLds32, 2>)
+                            : reinterpret_cast<const void*>(&vn6_tile_kernel<TX, TY, TZ, kGrainGlobal, 2>);
+        }
     }
     fits = (int64_t)bytes <= limit;
     return true;
@@ -371,16 +388,18 @@ bool pick(const Tiling& t, int32_t Q, bool& fits, const void*& fn, size_t& bytes
 
 }  // namespace
 
-bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes) {
+bool vn6_kernel_for(const Tiling& t, int32_t Q, const void** fn, size_t* lds_bytes, int* per_cu) {
     bool fits = false;
     const void* f = nullptr;
     size_t bytes = 0;
-    const bool known = pick<64, 16, 16>(t, Q, fits, f, bytes) || pick<32, 32, 16>(t, Q, fits, f, bytes) ||
-                       pick<32, 16, 16>(t, Q, fits, f, bytes) || pick<16, 16, 16>(t, Q, fits, f, bytes) ||
-                       pick<64, 16, 8>(t, Q, fits, f, bytes);
+    int pc = 1;
+    const bool known = pick<64, 16, 16>(t, Q, fits, f, bytes, pc) || pick<32, 32, 16>(t, Q, fits, f, bytes, pc) ||
+                       pick<32, 16, 16>(t, Q, fits, f, bytes, pc) || pick<16, 16, 16>(t, Q, fits, f, bytes, pc) ||
+                       pick<64, 16, 8>(t, Q, fits, f, bytes, pc);
     if (!known || !fits) return false;
     *fn = f;
     *lds_bytes = bytes;
+    *per_cu = pc;
     return true;
 }
 

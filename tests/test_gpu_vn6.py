@@ -11,7 +11,8 @@ trials, Sec. 4 Red/Black passes).
 * a caller's buffer (launch counts of either parity, so single-pass
   launches starting on either colour) and values outside [0, Q) that stay
   inert;
-* the default tiling of the 256^3 workload takes this kernel.
+* the default tiling of the 256^3 workload (32x16x16, two workgroups per
+  CU) takes this kernel.
 """
 import numpy as np
 import pytest
@@ -78,11 +79,14 @@ def test_wide_energy_spread_reads_grains_from_global_memory(tiling):
     assert tr_a == tr_g
 
 
-@pytest.mark.parametrize("dims,tiling", [((128, 128, 128), (16, 16, 16, 1)), ((144, 128, 128), (16, 16, 16, 1)),
-                                         ((144, 128, 128), (16, 16, 16, -1))])
+@pytest.mark.parametrize("dims,tiling", [((256, 128, 128), (16, 16, 16, 1)), ((144, 128, 128), (16, 16, 16, 1)),
+                                         ((144, 128, 128), (16, 16, 16, -1)), ((256, 256, 128), (32, 16, 16, 1)),
+                                         ((320, 128, 128), (64, 16, 16, 1)), ((320, 128, 128), (64, 16, 16, -1))])
 def test_workgroups_walk_several_tiles(dims, tiling):
-    """More tiles than workgroups (one per CU): each workgroup walks several
-    tiles, prefetching the next box; 576 tiles do not split evenly."""
+    """More tiles than workgroups: with two workgroups per CU (16^3 and
+    32x16x16 tiles) each walks several tiles, loading the next box after
+    storing one; with one per CU (64x16x16) each walks several, prefetching
+    the next box during the passes.  576 and 320 tiles do not split evenly."""
     Q, kT, seed = 6000, 0.6, 17
     B = synth.quantise(0.15 * (0.27 + 0.23 * np.random.default_rng(4).random(Q)))
     say(f"[gpu] vn6 several tiles per workgroup dims={dims} tiling={tiling}")
@@ -120,4 +124,5 @@ def test_wrapped_buffer_parities_and_inert_values():
 def test_default_3d_tiling_takes_the_compiled_kernel():
     w = synth.schmid_3d_256()
     with hmc.Lattice(w.dims, w.nbr, w.n_grains, spin=w.spin) as lat:
-        assert tuple(hmc.hmc_get_tiling(lat.h)) == (64, 16, 16, 1)
+        assert tuple(hmc.hmc_get_tiling(lat.h)) == (32, 16, 16, 1)
+        assert hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED
