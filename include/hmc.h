@@ -255,9 +255,10 @@ hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
  * (the default): the six-neighbour 16-bit model with neighbour trials, one
  * bond energy and grain energies runs a kernel compiled for its tile
  * (64x16x16, 32x32x16, 32x16x16, 16x16x16 or 64x16x8; one or two colour
- * passes per launch, lattice x side a multiple of 4), everything else the
- * general tile kernel; HMC_KERNEL_GENERIC: always the general kernel.  The
- * spins do not depend on the choice.  Errors: INVAL. */
+ * passes per launch, lattice x side a multiple of 4; 32x16x16, the default
+ * tile of such lattices, 16x16x16 and 64x16x8 run two workgroups per CU),
+ * everything else the general tile kernel; HMC_KERNEL_GENERIC: always the
+ * general kernel.  The spins do not depend on the choice.  Errors: INVAL. */
 enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1, HMC_KERNEL_COMPILED = 2 };
 hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);
 /* The kernel the next full sweep launch of L will run: HMC_KERNEL_COMPILED

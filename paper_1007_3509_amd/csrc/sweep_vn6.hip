@@ -333,9 +333,11 @@ vn6_tile_kernel(Vn6Args a) {
             else pass(std::integral_constant<int, 2>{}, c, t, p & 1u);
         }
 
-        // The next box has long arrived: wait for it here, before the stores,
-        // so that nothing later (the commit, the next prefetch into the same
-        // registers) has to wait for the stores themselves to complete.
+        // Every vector load of this workgroup has arrived by now (with one
+        // workgroup per CU that includes the next box, issued before the
+        // passes): wait for them here, before the stores, so that nothing
+        // later (the commit, the next box loaded into the same registers) has
+        // to wait for the stores themselves to complete.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         // The tile back to global memory, 8-byte words.
         constexpr int TW4 = TX / 4;
