@@ -297,6 +297,7 @@ struct hmc_ensemble_s {
     bool tiling_explicit = false;
     bool prepared = false;
     int32_t maxQ = 0;
+    bool vec = false;                   // members staged four 16-bit spins per 8-byte access
     void* d_tiles = nullptr;            // uint2 (lattice, tile) per tile
     size_t tiles_bytes = 0;
     uint32_t ntiles = 0;

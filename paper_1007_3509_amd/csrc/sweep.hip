@@ -681,13 +681,12 @@ Layout box_layout(int nbr, int ndim, size_t spin_bytes, int32_t maxQ, const Tili
     return o;
 }
 
-// Four 16-bit spins per 8-byte access along x: needs checkerboard int16
-// lattices whose tiles and x side are multiples of 4 and 8-byte aligned
-// spin buffers (a borrowed buffer may be aligned to 2 bytes only).
+// Four 16-bit spins per 8-byte access along x: needs int16 lattices whose
+// tiles and x side are multiples of 4 and 8-byte aligned spin buffers (a
+// borrowed buffer may be aligned to 2 bytes only).
 bool vec_ok(const hmc_lattice* L, const Tiling& t) {
-    return L->desc.spin == HMC_I16 && (L->desc.nbr == HMC_VN4 || L->desc.nbr == HMC_VN6) && t.tx % 4 == 0 &&
-           L->desc.dims[0] % 4 == 0 && reinterpret_cast<uintptr_t>(L->spins[0]) % 8 == 0 &&
-           reinterpret_cast<uintptr_t>(L->spins[1]) % 8 == 0;
+    return L->desc.spin == HMC_I16 && t.tx % 4 == 0 && L->desc.dims[0] % 4 == 0 &&
+           reinterpret_cast<uintptr_t>(L->spins[0]) % 8 == 0 && reinterpret_cast<uintptr_t>(L->spins[1]) % 8 == 0;
 }
 
 Layout box_layout(const hmc_lattice* L, const Tiling& t, int passes) {
@@ -1095,7 +1094,18 @@ hmc_status ensemble_prepare(hmc_ensemble* E) {
         E->lats_bytes = E->lats.size() * sizeof(EnsLat);
         HMC_TRY(dev_alloc(&E->d_lats, E->lats_bytes, "ensemble descriptors"));
     }
-    const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C, false);
+    // four spins per 8-byte access when every member allows it and the
+    // padded box still fits (the tile choice above did not pad)
+    E->vec = true;
+    for (const hmc_lattice* L : E->lats) E->vec = E->vec && vec_ok(L, E->tiling);
+    if (E->vec) {
+        for (int passes = 1; passes <= E->tiling.k * L0->C; ++passes) {
+            const Layout v = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, passes, true);
+            E->vec = E->vec && (int64_t)v.bytes <= lds_limit_bytes() && v.BX <= 1023;
+        }
+    }
+    const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, maxQ, E->tiling, E->tiling.k * L0->C,
+                                  E->vec);
     // resident workgroups per CU: two 1024-thread groups fill the wave slots;
     // the LDS of a CU (equal to the per-group limit on gfx950) may allow fewer
     const int per_cu = std::max(1, std::min(2, (int)(lds_limit_bytes() / std::max<size_t>(lay.bytes, 1))));
@@ -1156,7 +1166,7 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         while (remaining > 0 && err == hipSuccess) {
             const int k = std::min<int32_t>(E->tiling.k, remaining);
             const int passes = k * C;
-            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes, false);
+            const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes, E->vec);
             const bool swar = use_swar(L0->desc.nbr, L0->desc.spin, lay.BX);
             RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes, swar);
             const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true, swar);
