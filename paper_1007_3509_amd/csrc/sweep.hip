@@ -383,9 +383,13 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
             // Checkerboard, 16-bit spins: a lane takes 4 consecutive sites of a
             // row as one 64-bit word, XORs it with its four (six) neighbour
             // words and tests the two colour-c fields.
+            // Moore8 and Moore26: a pass takes the rows of one y (and z)
+            // parity only, and in them the sites of one x parity
+            constexpr bool kRowParity = NBR == HMC_MOORE8 || NBR == HMC_MOORE26;
             const uint32_t s_lo = lox >> 2, s_hi = (g.BX - lox - 1) >> 2;
             const uint32_t nseg = s_hi - s_lo + 1;
-            const uint32_t totalS = nseg * Wy * Wz;
+            const uint32_t rows_pl = kRowParity ? Wy / 2 : Wy;   // enumerated rows per plane
+            const uint32_t totalS = nseg * rows_pl * (kRowParity && D == 3 ? Wz / 2 : Wz);
             const uint32_t plane = g.BX * g.BY;
             const uint32_t pbase = (px + py + pz) & 1u;
             // two words per lane and round: half the rounds, one LDS atomic
@@ -400,14 +404,46 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                     const uint32_t rr = fdiv(f, m_row);
                     const uint32_t sg = s_lo + (f - __umul24(rr, nseg));
                     const uint32_t pl = (D == 3) ? fdiv(rr, m_rows) : 0u;
-                    const uint32_t v = lo + (rr - __umul24(pl, Wy));
-                    const uint32_t w = loz + pl;
+                    const uint32_t ri = rr - __umul24(pl, rows_pl);
+                    const uint32_t v = kRowParity ? lo + 2 * ri + ((cy ^ (lo + py)) & 1u) : lo + ri;
+                    const uint32_t w = (kRowParity && D == 3) ? loz + 2 * pl + ((cz ^ (loz + pz)) & 1u) : loz + pl;
                     const uint32_t row = __umul24(g.BX, v + __umul24(g.BY, w));
                     const uint32_t u0 = 4 * sg;
+                    // first colour-c field of the word
+                    const uint32_t k = kRowParity ? ((cx ^ px) & 1u) : ((c ^ (v + w + pbase)) & 1u);
                     const uint64_t S = *reinterpret_cast<const uint64_t*>(box + row + u0);
                     uint64_t x;   // per 16-bit field: nonzero where a neighbour differs
                     if (a.uniform) {
                         x = ~0ull;
+                    } else if constexpr (kRowParity) {
+                        // the word's neighbour sites: the words of the rows
+                        // around it (3 in 2D, 9 in 3D), and all of those rows
+                        // shifted one site each way.  A colour-c field has one
+                        // x neighbour outside the word, before it (k = 0) or
+                        // after it (k = 1): one load per row.
+                        const uint32_t ue = k ? (u0 + 4 < g.BX ? u0 + 4 : g.BX - 1) : (u0 > 0 ? u0 - 1 : 0);
+                        uint32_t fl = 0, fh = 0;
+                        const uint32_t sl = (uint32_t)S, sh = (uint32_t)(S >> 32);
+                        constexpr int kDz = D == 3 ? 1 : 0;
+#pragma unroll
+                        for (int dz = -kDz; dz <= kDz; ++dz) {
+#pragma unroll
+                            for (int dy = -1; dy <= 1; ++dy) {
+                                const uint32_t rw = row + (uint32_t)(dy * (int)g.BX + dz * (int)plane);
+                                const bool centre = dy == 0 && dz == 0;
+                                const uint64_t W = centre ? S : *reinterpret_cast<const uint64_t*>(box + rw + u0);
+                                const uint32_t e = (uint16_t)box[rw + ue];
+                                const uint32_t wl = (uint32_t)W, wh = (uint32_t)(W >> 32);
+                                const uint32_t mid = __builtin_amdgcn_alignbit(wh, wl, 16);   // sites 1, 2
+                                fl |= (sl ^ ((wl << 16) | e)) | (sl ^ mid);
+                                fh |= (sh ^ mid) | (sh ^ __builtin_amdgcn_alignbit(e, wh, 16));
+                                if (!centre) {
+                                    fl |= sl ^ wl;
+                                    fh |= sh ^ wh;
+                                }
+                            }
+                        }
+                        x = ((uint64_t)fh << 32) | fl;
                     } else {
                         const uint64_t Up = *reinterpret_cast<const uint64_t*>(box + row - g.BX + u0);
                         const uint64_t Dn = *reinterpret_cast<const uint64_t*>(box + row + g.BX + u0);
@@ -426,7 +462,6 @@ __device__ __forceinline__ void process_tile(const LatArgs& a, const RunArgs& g,
                             x |= (S ^ Fr) | (S ^ Bk);
                         }
                     }
-                    const uint32_t k = (c ^ (v + w + pbase)) & 1u;   // first colour-c field
                     const uint32_t ua = u0 + k, ub = u0 + k + 2;
                     pa[j] = ua >= lox && ua < g.BX - lox && __builtin_amdgcn_ubfe((uint32_t)x, 16 * k, 16) != 0;
                     pb[j] = ub >= lox && ub < g.BX - lox && __builtin_amdgcn_ubfe((uint32_t)(x >> 32), 16 * k, 16) != 0;
@@ -619,10 +654,10 @@ const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair, b
                          : reinterpret_cast<const void*>(&sweep_tile_kernel<NBR, int32_t, false, false, false>);
 }
 
-// The 64-bit phase-1 path needs 16-bit spins, a checkerboard and rows of a
-// multiple of 4 sites (8-byte aligned words).
+// The 64-bit phase-1 path needs 16-bit spins and rows of a multiple of 4
+// sites (8-byte aligned words).
 bool use_swar(int nbr, int spin, uint32_t BX) {
-    return spin == HMC_I16 && (nbr == HMC_VN4 || nbr == HMC_VN6) && BX % 4 == 0;
+    return spin == HMC_I16 && BX % 4 == 0;
 }
 
 const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar, bool pair = false,
@@ -631,11 +666,15 @@ const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, boo
     case HMC_VN4:
         return swar ? kernel_for<HMC_VN4, true>(spin, grains_in_lds, ensemble, pair, field)
                     : kernel_for<HMC_VN4, false>(spin, grains_in_lds, ensemble, pair, field);
-    case HMC_MOORE8: return kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble, pair, field);
+    case HMC_MOORE8:
+        return swar ? kernel_for<HMC_MOORE8, true>(spin, grains_in_lds, ensemble, pair, field)
+                    : kernel_for<HMC_MOORE8, false>(spin, grains_in_lds, ensemble, pair, field);
     case HMC_VN6:
         return swar ? kernel_for<HMC_VN6, true>(spin, grains_in_lds, ensemble, pair, field)
                     : kernel_for<HMC_VN6, false>(spin, grains_in_lds, ensemble, pair, field);
-    default: return kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble, pair, field);
+    default:
+        return swar ? kernel_for<HMC_MOORE26, true>(spin, grains_in_lds, ensemble, pair, field)
+                    : kernel_for<HMC_MOORE26, false>(spin, grains_in_lds, ensemble, pair, field);
     }
 }
 
@@ -723,7 +762,7 @@ RunArgs run_args(const Layout& lay, int nbr, const Tiling& t, int passes, bool s
         if (swar) {   // rows of 4-site segments
             const uint32_t nseg = ((lay.BX - lox - 1) >> 2) - (lox >> 2) + 1;
             g.m_pass[ps][0] = magic(nseg);
-            g.m_pass[ps][1] = magic(Wy);
+            g.m_pass[ps][1] = magic(nbr == HMC_MOORE8 || nbr == HMC_MOORE26 ? Wy / 2 : Wy);
         } else {
             g.m_pass[ps][0] = magic(Wx / 2);
             g.m_pass[ps][1] = magic(cb ? Wy : Wy / 2);
