@@ -655,9 +655,11 @@ const void* kernel_for(int spin, bool grains_in_lds, bool ensemble, bool pair, b
 }
 
 // The 64-bit phase-1 path needs 16-bit spins and rows of a multiple of 4
-// sites (8-byte aligned words).
-bool use_swar(int nbr, int spin, uint32_t BX) {
-    return spin == HMC_I16 && BX % 4 == 0;
+// sites (8-byte aligned words).  Moore8 takes it from 128-site tiles on: the
+// 64-member ensemble (128x128 tiles) gains 2.48 -> 2.57e11 site updates/s,
+// while its members swept one by one with 64x64 tiles lose 1.10 -> 0.96e11.
+bool use_swar(int nbr, int spin, uint32_t BX, int tx) {
+    return spin == HMC_I16 && BX % 4 == 0 && (nbr != HMC_MOORE8 || tx >= 128);
 }
 
 const void* kernel_ptr(int nbr, int spin, bool grains_in_lds, bool ensemble, bool swar, bool pair = false,
@@ -1026,7 +1028,7 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     int64_t gp0 = 0;   // passes done in this call
     for (const int passes : chunks) {
         const Layout lay = box_layout(L, t, passes);
-        const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX);
+        const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX, t.tx);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
         const void* kfn = vn6 ? vfn : kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair,
                                                  L->field);
@@ -1206,7 +1208,7 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
             const int k = std::min<int32_t>(E->tiling.k, remaining);
             const int passes = k * C;
             const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes, E->vec);
-            const bool swar = use_swar(L0->desc.nbr, L0->desc.spin, lay.BX);
+            const bool swar = use_swar(L0->desc.nbr, L0->desc.spin, lay.BX, E->tiling.tx);
             RunArgs g = run_args(lay, L0->desc.nbr, E->tiling, passes, swar);
             const void* kfn = kernel_ptr(L0->desc.nbr, L0->desc.spin, lay.grains_in_lds, true, swar);
             const EnsLat* dl = static_cast<const EnsLat*>(E->d_lats);
