@@ -77,6 +77,12 @@ SMALL = [
     ((20, 14, 12), hmc.HMC_VN6, 5, 1.5, 6, hmc.HMC_I32, 1),
     ((12, 10, 8), hmc.HMC_MOORE26, 12, 0.8, 7, hmc.HMC_I16, 0),
     ((8, 6, 10), hmc.HMC_MOORE26, 4, 3.0, 3, hmc.HMC_I32, 1),
+    # degenerate temperatures: almost every uphill trial rejected, almost every one accepted
+    ((64, 48), hmc.HMC_VN4, 40, 1e-3, 9, hmc.HMC_I16, 0),
+    ((64, 48), hmc.HMC_MOORE8, 40, 40.0, 9, hmc.HMC_I16, 0),
+    ((16, 12, 8), hmc.HMC_VN6, 20, 1e-3, 6, hmc.HMC_I32, 0),
+    ((64, 32, 32), hmc.HMC_VN6, 50, 40.0, 5, hmc.HMC_I16, 0),
+    ((64, 32, 32), hmc.HMC_VN6, 50, 1e-3, 5, hmc.HMC_I16, 0),
 ]
 
 
