@@ -218,3 +218,32 @@ def test_large_ensemble_takes_128_tiles_and_matches_singles():
         hmc.hmc_ensemble_free(E)
         for l in a + b:
             l.close()
+
+
+@pytest.mark.parametrize("Q", [300, 6000])
+def test_compiled_moore8_ensemble_tiles_equal_oracle(Q):
+    """16-bit Moore8 members in 128x128 tiles with 3 MC steps per launch run
+    the ensemble kernel compiled for that tile (grain energies in LDS for
+    Q = 300, from global memory for Q = 6000); 7 MC steps = two such
+    launches and a short general one.  Every member equals the oracle."""
+    specs = [((256, 256), Q, 21), ((128, 384), Q, 22), ((384, 128), Q, 23)]
+    kT = np.array([0.4, 0.7, 1.1], np.float32)
+    seeds = np.array([71, 72, 73], np.uint64)
+    n_mcs = 7
+    say(f"[gpu] compiled Moore8 ensemble tiles, Q={Q}")
+    lats = _members(specs)
+    starts = [l.spins().astype(np.int32) for l in lats]
+    E = hmc.hmc_ensemble_create(lats)
+    try:
+        hmc.hmc_ensemble_set_tiling(E, 128, 128, 1, 3)
+        hmc.hmc_ensemble_sweep(E, kT, seeds, n_mcs)
+        hmc.hmc_ensemble_synchronize(E)
+        got = [l.spins().astype(np.int32) for l in lats]
+    finally:
+        hmc.hmc_ensemble_free(E)
+    for i, ((dims, G, vseed), lat) in enumerate(zip(specs, lats)):
+        B = synth.quantise(0.2 * (0.27 + 0.23 * np.random.default_rng(vseed).random(G)))
+        want = oracle.sweep(starts[i], hmc.HMC_MOORE8, dims, B, float(kT[i]), n_mcs, int(seeds[i]), threads=THREADS)
+        assert not np.array_equal(want, starts[i])
+        assert np.array_equal(got[i], want), f"member {i}: {int(np.sum(got[i] != want))} sites differ"
+        lat.close()
