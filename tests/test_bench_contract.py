@@ -49,9 +49,10 @@ def test_sweep_profiles_are_machine_readable(workload):
 
 
 def test_ensemble_and_nfold_profiles_are_machine_readable():
-    f = _fields(os.path.join(ROOT, "profiles", "ensemble_kernel_ensemble_moore8.md"))
+    f = _fields(os.path.join(ROOT, "profiles", "ens_m8_kernel_ensemble_moore8.md"))
     assert float(f["traffic_bytes_per_launch"]) > 0 and float(f["valu_wave_instructions_per_launch"]) > 0
-    assert bench.measured_profile("ensemble_moore8", (1, 1, 1, 1), kernel="ensemble_kernel") == {}
+    assert bench.measured_profile("ensemble_moore8", (1, 1, 1, 1), kernel="ens_m8_kernel") == {}
+    assert bench.measured_profile("ensemble_moore8", (128, 128, 1, 3), kernel="ens_m8_kernel")
     g = _fields(os.path.join(ROOT, "profiles", "nfold_kernel_nfold_ensemble_128.md"))
     assert re.fullmatch(r"[0-9a-f]{64}", g["kernel_source_sha256"])
     assert float(g["traffic_bytes_per_launch"]) > 0 and float(g["valu_wave_instructions_per_launch"]) > 0
