@@ -269,7 +269,10 @@ def main():
     su_per_launch = su / max(launches, 1)
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
     tiling = lat.tiling()
-    kname = "vn6_tile_kernel" if hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED else "sweep_tile_kernel"
+    if hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED:
+        kname = "vn6_tile_kernel" if len(w.dims) == 3 else "lat2d_kernel"
+    else:
+        kname = "sweep_tile_kernel"
     prof = measured_profile(w.name, tiling, kernel=kname)
     traffic = prof.get("traffic_bytes_per_launch")
     valu = prof.get("valu_wave_instructions_per_launch")
@@ -416,9 +419,9 @@ def bench_ensemble(args, hmc):
     launch_s = kernel_ms / 1e3 / max(launches, 1)
     su_launch = su_prof / max(launches, 1)
     achieved = su_launch * bpsu / launch_s / 1e9
-    # 16-bit Moore8 members in 128x128 tiles, 3 MC steps per launch: the
+    # 16-bit Moore8 members in 128x128 tiles with 3 MC steps per launch: the
     # library's kernel compiled for that tile runs every full launch
-    kname = ("ens_m8_kernel" if members[0].nbr == hmc.HMC_MOORE8 and tuple(tiling) == (128, 128, 1, 3)
+    kname = ("ens2d_kernel" if members[0].nbr == hmc.HMC_MOORE8 and tuple(tiling) == (128, 128, 1, 3)
              else "ensemble_kernel")
     prof = measured_profile("ensemble_moore8", tuple(tiling), kernel=kname)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",

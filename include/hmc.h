@@ -252,13 +252,15 @@ hmc_status hmc_set_tiling(hmc_lattice *L, int32_t tx, int32_t ty, int32_t tz, in
 hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
 
 /* Which sweep kernel runs the Red/Black passes (Sec. 4).  HMC_KERNEL_AUTO
- * (the default): the six-neighbour 16-bit model with neighbour trials, one
- * bond energy and grain energies runs a kernel compiled for its tile
- * (64x16x16, 32x32x16, 32x16x16, 16x16x16 or 64x16x8; one or two colour
- * passes per launch, lattice x side a multiple of 4; 32x16x16, the default
- * tile of such lattices, 16x16x16 and 64x16x8 run two workgroups per CU),
- * everything else the general tile kernel; HMC_KERNEL_GENERIC: always the
- * general kernel.  The spins do not depend on the choice.  Errors: INVAL. */
+ * (the default): 16-bit lattices with neighbour trials, one bond energy and
+ * grain energies (lattice x side a multiple of 4) run a kernel compiled for
+ * their tile where there is one: six-neighbour 64x16x16, 32x32x16,
+ * 32x16x16, 16x16x16 or 64x16x8 with one or two colour passes per launch
+ * (32x16x16, the default tile of such lattices, 16x16x16 and 64x16x8 run two
+ * workgroups per CU); four-neighbour 128x128 with 6 MC steps per launch,
+ * eight-neighbour 128x128 with 3 (launches of fewer passes, at the end of a
+ * call, take the general kernel); everything else the general tile kernel.  HMC_KERNEL_GENERIC: always the general kernel.  The spins do not
+ * depend on the choice.  Errors: INVAL. */
 enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1, HMC_KERNEL_COMPILED = 2 };
 hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);
 /* The kernel the next full sweep launch of L will run: HMC_KERNEL_COMPILED

@@ -687,7 +687,8 @@ hmc_status hmc_get_sweep_kernel(const hmc_lattice* L, int32_t* which) {
     const void* fn = nullptr;
     size_t bytes = 0;
     int per_cu = 1;
-    *which = compiled_vn6(L, t, &fn, &bytes, &per_cu) ? HMC_KERNEL_COMPILED : HMC_KERNEL_GENERIC;
+    *which = (compiled_vn6(L, t, &fn, &bytes, &per_cu) || compiled2d(L, t, &fn, &bytes)) ? HMC_KERNEL_COMPILED
+                                                                                           : HMC_KERNEL_GENERIC;
     return HMC_OK;
 }
 

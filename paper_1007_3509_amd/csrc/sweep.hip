@@ -628,22 +628,26 @@ ensemble_kernel(RunArgs g, const EnsLat* __restrict__ lats, const uint2* __restr
 }
 
 // ----------------------------------------------------------------------
-// Ensembles of 16-bit Moore8 lattices in T x T tiles, K MC steps (4K colour
+// 16-bit VN4 and Moore8 lattices in TX x TY tiles, K MC steps (K*C colour
 // passes) per launch, neighbour trials: the method, random numbers and
-// integer acceptance of ensemble_kernel with the box geometry fixed at
-// compile time, so every index computation is a constant or a shift.  Per
-// pass, phase 1 walks the rows of the pass's y parity in 4-site words (a
-// fixed word column per thread), phase 2 runs the trials of the queued sites.
+// integer acceptance of process_tile with the box geometry fixed at compile
+// time, so every index computation is a constant or a shift.  Per pass,
+// phase 1 walks the rows of the pass region (Moore8: only those of the
+// pass's y parity) in 4-site words from a fixed word column per thread,
+// phase 2 runs the trials of the queued sites.  One routine per tile, run by
+// a single-lattice kernel (one tile per workgroup) and by a persistent
+// ensemble kernel over the tile table of all members.
 
 constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
-template <int T, int K>
-struct M8Geom {
-    static constexpr int C = 4, P = K * C, H = P, HX = (P + 3) & ~3;
-    static constexpr int BX = T + 2 * HX, BY = T + 2 * H, NBOX = BX * BY, NW = BX / 4;
+template <int NBR, int TX, int TY, int K>
+struct Geom2D {
+    static constexpr int M = Traits<NBR>::M, C = Traits<NBR>::C;
+    static constexpr int P = K * C, H = P, HX = (P + 3) & ~3;
+    static constexpr int BX = TX + 2 * HX, BY = TY + 2 * H, NBOX = BX * BY, NW = BX / 4;
     static constexpr int NWORDS = NBOX / 4, PRE = (NWORDS + kThreads - 1) / kThreads;
-    // the class of the first (largest) pass region: a quarter of it
-    static constexpr int QCAP = (BX - 2 * (1 + HX - H)) * (BY - 2) / 4 + 1;
+    // the colour class of the first (largest) pass region
+    static constexpr int QCAP = (BX - 2 * (1 + HX - H)) * (BY - 2) / C + 1;
     static constexpr size_t kBoundOff = 0;                                  // uint32[2 * kBoundPairs]
     static constexpr size_t kCountOff = 8 * (size_t)kBoundPairs;            // uint32[2]
     static constexpr size_t kOffsetOff = kCountOff + 16;                    // int32[8]: neighbour offsets
@@ -652,17 +656,34 @@ struct M8Geom {
     static constexpr size_t kBoxOff = kRowOff + align16(4 * (size_t)BY);    // int16[NBOX]
     static constexpr size_t kQueueOff = kBoxOff + align16(2 * (size_t)NBOX);
     static constexpr size_t kGrainOff = kQueueOff + align16(4 * (size_t)QCAP);   // int32[Q] (grains in LDS)
-    static_assert(T % 4 == 0 && HX >= H, "tile and halo");
+    static_assert(NBR == HMC_VN4 || NBR == HMC_MOORE8, "2D neighbourhoods");
+    static_assert(TX % 4 == 0 && HX >= H, "tile and halo");
     static_assert(NBOX < 65536 && BY < 65536, "queue entries pack the box index and row in 16 bits each");
 };
 
-template <int T, int K, bool kGrainsInLds>
-__global__ void __launch_bounds__(kThreads)
-ens_m8_kernel(const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, uint32_t ntiles, uint32_t j,
-              uint32_t k) {
-    using G = M8Geom<T, K>;
-    constexpr int BX = G::BX, BY = G::BY, NW = G::NW, H = G::H, HX = G::HX, P = G::P;
-    extern __shared__ __align__(16) unsigned char smem[];
+// Box offsets of the neighbours in LDS, written once per workgroup before
+// its first tile (read by the trials after the tile's first barrier).
+template <int NBR, int TX, int TY, int K>
+__device__ __forceinline__ void init_offsets2d(unsigned char* smem) {
+    using G = Geom2D<NBR, TX, TY, K>;
+    constexpr int BX = G::BX;
+    int32_t* noff = reinterpret_cast<int32_t*>(smem + G::kOffsetOff);
+    const uint32_t tid = threadIdx.x;
+    if (tid < (uint32_t)G::M) {   // neighbour k: +x -x +y -y (+1,+1) (-1,-1) (+1,-1) (-1,+1)
+        const int sgn = (tid & 1u) ? -1 : 1;
+        noff[tid] = tid < 2 ? sgn : (tid < 4 ? sgn * BX : (tid < 6 ? sgn * (1 + BX) : sgn * (1 - BX)));
+    }
+}
+
+// One tile of lattice a (MC step t0 at its first pass, colour 0), box from
+// src, interior to dst.  Ends past its last LDS access of the tile.
+template <int NBR, int TX, int TY, int K, bool kGrainsInLds>
+__device__ __forceinline__ void tile2d(const LatArgs& a, const int16_t* __restrict__ src, int16_t* __restrict__ dst,
+                                       uint32_t t0, uint32_t tx, uint32_t ty, unsigned char* smem) {
+    using G = Geom2D<NBR, TX, TY, K>;
+    constexpr int BX = G::BX, BY = G::BY, NW = G::NW, H = G::H, HX = G::HX, P = G::P, M = G::M, C = G::C;
+    constexpr bool kMoore = NBR == HMC_MOORE8;
+    constexpr int kTrialUnroll = 2;   // trials in flight per thread
     uint32_t* tbound = reinterpret_cast<uint32_t*>(smem + G::kBoundOff);
     uint32_t* qcount = reinterpret_cast<uint32_t*>(smem + G::kCountOff);
     int32_t* noff = reinterpret_cast<int32_t*>(smem + G::kOffsetOff);
@@ -676,182 +697,231 @@ ens_m8_kernel(const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint64_t lanes_below = (1ull << lane) - 1ull;
-    if (tid < 8) {   // box offset of neighbour k: +x -x +y -y (+1,+1) (-1,-1) (+1,-1) (-1,+1)
-        const int sgn = (tid & 1u) ? -1 : 1;
-        noff[tid] = tid < 2 ? sgn : (tid < 4 ? sgn * BX : (tid < 6 ? sgn * (1 + BX) : sgn * (1 - BX)));
-    }
-
-    for (uint32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
-        const uint2 tl = tiles[i];
-        const EnsLat& e = lats[tl.x];
-        const LatArgs& a = e.a;
-        const uint32_t sel = (e.cur ^ j) & 1u;
-        const int16_t* __restrict__ src = static_cast<const int16_t*>(e.buf[sel]);
-        int16_t* __restrict__ dst = static_cast<int16_t*>(e.buf[sel ^ 1u]);
-        const uint32_t t0 = e.t_base + j * k;
-        const uint32_t Lx = a.Lx, Ly = a.Ly;
-        const uint32_t tx = tl.y % a.ntx, ty = tl.y / a.ntx;
-        const int32_t x0 = (int32_t)(tx * T) - HX, y0 = (int32_t)(ty * T) - H;
-        const int32_t* __restrict__ Bq = kGrainsInLds ? sB : a.B;
-        for (uint32_t u = tid; u < (uint32_t)BX; u += kThreads) gx[u] = wrap_coord(x0 + (int32_t)u, Lx);
-        for (uint32_t v = tid; v < (uint32_t)BY; v += kThreads) rowL[v] = Lx * wrap_coord(y0 + (int32_t)v, Ly);
-        for (uint32_t r = tid; r < 2u * (uint32_t)a.nbound; r += kThreads) tbound[r] = a.Tb[r];
-        if constexpr (kGrainsInLds)
-            for (uint32_t q = tid; q < (uint32_t)a.Q; q += kThreads) sB[q] = a.B[q];
-        if (tid < 2) qcount[tid] = 0;
-        __syncthreads();
-        {   // the box, four spins per 8-byte access (rows start at a multiple of 4)
-            uint64_t w[G::PRE];
+    const uint32_t Lx = a.Lx, Ly = a.Ly;
+    const int32_t x0 = (int32_t)(tx * TX) - HX, y0 = (int32_t)(ty * TY) - H;
+    const int32_t* __restrict__ Bq = kGrainsInLds ? sB : a.B;
+    for (uint32_t u = tid; u < (uint32_t)BX; u += kThreads) gx[u] = wrap_coord(x0 + (int32_t)u, Lx);
+    for (uint32_t v = tid; v < (uint32_t)BY; v += kThreads) rowL[v] = Lx * wrap_coord(y0 + (int32_t)v, Ly);
+    for (uint32_t r = tid; r < 2u * (uint32_t)a.nbound; r += kThreads) tbound[r] = a.Tb[r];
+    if constexpr (kGrainsInLds)
+        for (uint32_t q = tid; q < (uint32_t)a.Q; q += kThreads) sB[q] = a.B[q];
+    if (tid < 2) qcount[tid] = 0;
+    __syncthreads();
+    {   // the box, four spins per 8-byte access (rows start at a multiple of 4)
+        uint64_t w[G::PRE];
 #pragma unroll
-            for (int q = 0; q < G::PRE; ++q) {
-                const uint32_t e2 = tid + (uint32_t)q * kThreads;
-                const uint32_t ec = e2 < (uint32_t)G::NWORDS ? e2 : 0u;
-                const uint32_t r = ec / NW, u4 = ec - r * NW;
-                w[q] = *reinterpret_cast<const uint64_t*>(src + gx[4 * u4] + rowL[r]);
-            }
-#pragma unroll
-            for (int q = 0; q < G::PRE; ++q) {
-                const uint32_t e2 = tid + (uint32_t)q * kThreads;
-                if (e2 < (uint32_t)G::NWORDS) boxw[e2] = w[q];
-            }
+        for (int q = 0; q < G::PRE; ++q) {
+            const uint32_t e2 = tid + (uint32_t)q * kThreads;
+            const uint32_t ec = e2 < (uint32_t)G::NWORDS ? e2 : 0u;
+            const uint32_t r = ec / NW, u4 = ec - r * NW;
+            w[q] = *reinterpret_cast<const uint64_t*>(src + gx[4 * u4] + rowL[r]);
         }
-        __syncthreads();
-
-        const uint32_t px = (uint32_t)x0 & 1u, py = (uint32_t)y0 & 1u;   // colour parity of box column/row 0
-        unsigned long long drawn = 0;
-        for (int p = 0; p < P; ++p) {
-            const uint32_t c = (uint32_t)p & 3u, t = t0 + ((uint32_t)p >> 2);
-            const uint32_t cx = c & 1u, cy = c >> 1;
-            const uint32_t R = (uint32_t)p + 1u;           // ring: the pass region is R sites inside the box
-            const uint32_t lox = R + (uint32_t)(HX - H);
-            const uint32_t s_lo = lox >> 2, s_hi = ((uint32_t)BX - lox - 1u) >> 2, nseg = s_hi - s_lo + 1u;
-            const uint32_t nrows = ((uint32_t)BY - 2u * R) / 2u;   // rows of the pass's y parity
-            const uint32_t vpar = (cy ^ (R + py)) & 1u;
-            const uint32_t rpi = kThreads / nseg;
-            const uint32_t sg = s_lo + tid % nseg, i0 = tid / nseg;
-            const bool tact = tid < rpi * nseg;
-            const uint32_t kf = (cx ^ px) & 1u;            // first colour-c field of a word
-            const uint32_t ua = 4 * sg + kf, ub = ua + 2;
-            const bool oka = ua >= lox && ua < (uint32_t)BX - lox, okb = ub >= lox && ub < (uint32_t)BX - lox;
-            // the one x neighbour outside the word that a colour-c field has
-            const uint32_t ue = kf ? (4 * sg + 4 < (uint32_t)BX ? 4 * sg + 4 : (uint32_t)BX - 1)
-                                   : (sg > 0 ? 4 * sg - 1 : 0u);
-            uint32_t* qc = &qcount[p & 1];
-            const uint32_t iters = (nrows + rpi - 1) / rpi;
-            for (uint32_t it = 0; it < iters; ++it) {
-                const uint32_t ir = i0 + it * rpi;
-                bool pa = false, pb = false;
-                uint32_t ea = 0, eb = 0;
-                if (tact && ir < nrows) {
-                    const uint32_t v = R + 2 * ir + vpar;
-                    const uint32_t wi = v * NW + sg;
-                    const uint64_t S = boxw[wi];
-                    const uint32_t sl = (uint32_t)S, sh = (uint32_t)(S >> 32);
-                    uint32_t fl = 0, fh = 0;
 #pragma unroll
-                    for (int dy = -1; dy <= 1; ++dy) {
-                        const uint64_t W = dy == 0 ? S : boxw[wi + dy * NW];
+        for (int q = 0; q < G::PRE; ++q) {
+            const uint32_t e2 = tid + (uint32_t)q * kThreads;
+            if (e2 < (uint32_t)G::NWORDS) boxw[e2] = w[q];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t px = (uint32_t)x0 & 1u, py = (uint32_t)y0 & 1u;   // colour parity of box column/row 0
+    unsigned long long drawn = 0;
+    for (int p = 0; p < P; ++p) {
+        const uint32_t c = (uint32_t)p % C, t = t0 + (uint32_t)p / C;
+        const uint32_t R = (uint32_t)p + 1u;           // ring: the pass region is R sites inside the box
+        const uint32_t lox = R + (uint32_t)(HX - H);
+        const uint32_t s_lo = lox >> 2, s_hi = ((uint32_t)BX - lox - 1u) >> 2, nseg = s_hi - s_lo + 1u;
+        // rows of the pass region (Moore8: of the pass's y parity only)
+        const uint32_t nrows = kMoore ? ((uint32_t)BY - 2u * R) / 2u : (uint32_t)BY - 2u * R;
+        const uint32_t vpar = kMoore ? ((c >> 1) ^ (R + py)) & 1u : 0u;
+        const uint32_t rpi = kThreads / nseg;
+        const uint32_t sg = s_lo + tid % nseg, i0 = tid / nseg;
+        const bool tact = tid < rpi * nseg;
+        const uint32_t u0 = 4 * sg;
+        // first colour-c field of a word: Moore8 x & 1 = c & 1 (the same in
+        // every row of the pass), VN4 (x + y) & 1 = c (alternating by row)
+        const uint32_t kf0 = kMoore ? ((c ^ px) & 1u) : ((c ^ (R + px + py)) & 1u);
+        // a colour-c field has one x neighbour outside the word: before it
+        // (first field 0) or after it (first field 1)
+        const uint32_t ue0 = kf0 ? (u0 + 4 < (uint32_t)BX ? u0 + 4 : (uint32_t)BX - 1) : (sg > 0 ? u0 - 1 : 0u);
+        const uint32_t ue1 = kf0 ? (sg > 0 ? u0 - 1 : 0u) : (u0 + 4 < (uint32_t)BX ? u0 + 4 : (uint32_t)BX - 1);
+        const uint32_t ua0 = u0 + kf0, ua1 = u0 + (kf0 ^ 1u);
+        const bool oka0 = ua0 >= lox && ua0 < (uint32_t)BX - lox, okb0 = ua0 + 2 >= lox && ua0 + 2 < (uint32_t)BX - lox;
+        const bool oka1 = ua1 >= lox && ua1 < (uint32_t)BX - lox, okb1 = ua1 + 2 >= lox && ua1 + 2 < (uint32_t)BX - lox;
+        uint32_t* qc = &qcount[p & 1];
+        const uint32_t iters = (nrows + rpi - 1) / rpi;
+        for (uint32_t it = 0; it < iters; ++it) {
+            const uint32_t ir = i0 + it * rpi;
+            bool pa = false, pb = false;
+            uint32_t ea = 0, eb = 0;
+            if (tact && ir < nrows) {
+                const uint32_t v = kMoore ? R + 2 * ir + vpar : R + ir;
+                const bool odd = !kMoore && (ir & 1u);   // VN4: every other row has the other first field
+                const uint32_t kf = odd ? kf0 ^ 1u : kf0;
+                const uint32_t ue = odd ? ue1 : ue0;
+                const uint32_t ua = odd ? ua1 : ua0;
+                const bool oka = odd ? oka1 : oka0, okb = odd ? okb1 : okb0;
+                const uint32_t wi = v * NW + sg;
+                const uint64_t S = boxw[wi];
+                const uint32_t sl = (uint32_t)S, sh = (uint32_t)(S >> 32);
+                uint32_t fl = 0, fh = 0;
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const uint64_t W = dy == 0 ? S : boxw[wi + dy * NW];
+                    const uint32_t wl = (uint32_t)W, wh = (uint32_t)(W >> 32);
+                    if (dy == 0 || kMoore) {   // the row shifted one site each way
                         const uint32_t ev = (uint16_t)box[(v + dy) * BX + ue];
-                        const uint32_t wl = (uint32_t)W, wh = (uint32_t)(W >> 32);
                         const uint32_t mid = __builtin_amdgcn_alignbit(wh, wl, 16);   // sites 1, 2
                         fl |= (sl ^ ((wl << 16) | ev)) | (sl ^ mid);
                         fh |= (sh ^ mid) | (sh ^ __builtin_amdgcn_alignbit(ev, wh, 16));
-                        if (dy != 0) {
-                            fl |= sl ^ wl;
-                            fh |= sh ^ wh;
-                        }
                     }
-                    pa = oka && __builtin_amdgcn_ubfe(fl, 16 * kf, 16) != 0;
-                    pb = okb && __builtin_amdgcn_ubfe(fh, 16 * kf, 16) != 0;
-                    ea = (v * BX + ua) | (v << 16);
-                    eb = ea + 2;
+                    if (dy != 0) {
+                        fl |= sl ^ wl;
+                        fh |= sh ^ wh;
+                    }
                 }
-                const uint64_t ma = __ballot(pa), mb = __ballot(pb);
-                const uint32_t na = (uint32_t)__popcll(ma);
-                const uint32_t n = na + (uint32_t)__popcll(mb);
-                if (n) {
-                    uint32_t base = 0;
-                    if (lane == 0) base = atomicAdd(qc, n);
-                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-                    if (pa) queue[base + (uint32_t)__popcll(ma & lanes_below)] = ea;
-                    if (pb) queue[base + na + (uint32_t)__popcll(mb & lanes_below)] = eb;
-                }
+                pa = oka && __builtin_amdgcn_ubfe(fl, 16 * kf, 16) != 0;
+                pb = okb && __builtin_amdgcn_ubfe(fh, 16 * kf, 16) != 0;
+                ea = (v * BX + ua) | (v << 16);
+                eb = ea + 2;
             }
-            __syncthreads();
-            const uint32_t count = *qc;
-            if (tid == 0) {
-                qcount[(p + 1) & 1] = 0;
-                drawn += count;
+            const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+            const uint32_t na = (uint32_t)__popcll(ma);
+            const uint32_t n = na + (uint32_t)__popcll(mb);
+            if (n) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(qc, n);
+                base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                if (pa) queue[base + (uint32_t)__popcll(ma & lanes_below)] = ea;
+                if (pb) queue[base + na + (uint32_t)__popcll(mb & lanes_below)] = eb;
             }
-            auto trial = [&](uint32_t en) __attribute__((always_inline)) {
-                const uint32_t idx = en & 0xFFFFu, row = en >> 16;
-                const uint32_t u = idx - row * BX;
-                const int32_t q = box[idx];
-                int32_t nb[8];
-                nb[0] = box[idx + 1];
-                nb[1] = box[idx - 1];
-                nb[2] = box[idx + BX];
-                nb[3] = box[idx - BX];
+        }
+        __syncthreads();
+        const uint32_t count = *qc;
+        if (tid == 0) {
+            qcount[(p + 1) & 1] = 0;
+            drawn += count;
+        }
+        auto trial = [&](uint32_t en) __attribute__((always_inline)) {
+            const uint32_t idx = en & 0xFFFFu, row = en >> 16;
+            const uint32_t u = idx - row * BX;
+            const int32_t q = box[idx];
+            int32_t nb[M];
+            nb[0] = box[idx + 1];
+            nb[1] = box[idx - 1];
+            nb[2] = box[idx + BX];
+            nb[3] = box[idx - BX];
+            if constexpr (M == 8) {
                 nb[4] = box[idx + 1 + BX];
                 nb[5] = box[idx - 1 - BX];
                 nb[6] = box[idx + 1 - BX];
                 nb[7] = box[idx - 1 + BX];
-                const uint32_t site = gx[u] + rowL[row];
-                const bool q_ok = (uint32_t)q < (uint32_t)a.Q;   // a value outside [0, Q) never moves
-                const int32_t bq = Bq[q_ok ? q : 0];
-                const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
-                const uint32_t kk = __umulhi(r.r0, 8u);
-                const int32_t qn = box[(int32_t)idx + noff[kk]];
-                if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
-                const int32_t dn = like_difference16<8>(nb, q, qn);
-                const int32_t dB = Bq[qn] - bq;
-                const int32_t d = a.J_fx * dn + dB;
-                bool accept = d <= 0;
-                if (!accept) {
-                    // T is non-increasing in d: the bucket's bounds decide almost every trial
-                    const int rowT = dn - a.dn_lo;
-                    const uint32_t col = (uint32_t)(dB + a.R);
-                    const uint32_t bucket = a.m_bw ? __umulhi(col, a.m_bw) : col / a.bw;
-                    const uint32_t bk = (uint32_t)rowT * (uint32_t)a.nb + bucket;
-                    if (r.r1 < tbound[2 * bk]) accept = true;
-                    else if (r.r1 < tbound[2 * bk + 1]) accept = r.r1 < a.T[rowT * a.TW + (int)col];
-                }
-                if (accept) box[idx] = (int16_t)qn;
-            };
-            for (uint32_t e0 = tid; e0 < count; e0 += 2 * kThreads) {
-#pragma unroll
-                for (int q2 = 0; q2 < 2; ++q2) {
-                    const uint32_t en = e0 + q2 * kThreads;
-                    if (en < count) trial(queue[en]);
-                }
             }
-            __syncthreads();
+            const uint32_t site = gx[u] + rowL[row];
+            const bool q_ok = (uint32_t)q < (uint32_t)a.Q;   // a value outside [0, Q) never moves
+            const int32_t bq = Bq[q_ok ? q : 0];
+            const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
+            const uint32_t kk = __umulhi(r.r0, (uint32_t)M);
+            const int32_t qn = box[(int32_t)idx + noff[kk]];
+            if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
+            const int32_t dn = like_difference16<M>(nb, q, qn);
+            const int32_t dB = Bq[qn] - bq;
+            const int32_t d = a.J_fx * dn + dB;
+            bool accept = d <= 0;
+            if (!accept) {
+                // T is non-increasing in d: the bucket's bounds decide almost every trial
+                const int rowT = dn - a.dn_lo;
+                const uint32_t col = (uint32_t)(dB + a.R);
+                const uint32_t bucket = a.m_bw ? __umulhi(col, a.m_bw) : col / a.bw;
+                const uint32_t bk = (uint32_t)rowT * (uint32_t)a.nb + bucket;
+                if (r.r1 < tbound[2 * bk]) accept = true;
+                else if (r.r1 < tbound[2 * bk + 1]) accept = r.r1 < a.T[rowT * a.TW + (int)col];
+            }
+            if (accept) box[idx] = (int16_t)qn;
+        };
+        for (uint32_t e0 = tid; e0 < count; e0 += kTrialUnroll * kThreads) {
+#pragma unroll
+            for (int q2 = 0; q2 < kTrialUnroll; ++q2) {
+                const uint32_t en = e0 + q2 * kThreads;
+                if (en < count) trial(queue[en]);
+            }
         }
-        if (a.trials && tid == 0) atomicAdd(&a.trials[blockIdx.x & (kTrialSlots - 1)], drawn);
-        // the tile back to global memory, 8-byte words
-        constexpr int TW4 = T / 4;
-        const uint32_t gx0 = gx[HX];
-        for (uint32_t e2 = tid; e2 < (uint32_t)(TW4 * T); e2 += kThreads) {
-            const uint32_t vv = e2 / TW4, u4 = e2 - vv * TW4;
-            const uint64_t val = boxw[(H + vv) * NW + HX / 4 + u4];
-            *reinterpret_cast<uint64_t*>(dst + gx0 + 4 * u4 + rowL[H + vv]) = val;
-        }
+        __syncthreads();
+    }
+    if (a.trials && tid == 0) atomicAdd(&a.trials[blockIdx.x & (kTrialSlots - 1)], drawn);
+    // the tile back to global memory, 8-byte words
+    constexpr int TW4 = TX / 4;
+    const uint32_t gx0 = gx[HX];
+    for (uint32_t e2 = tid; e2 < (uint32_t)(TW4 * TY); e2 += kThreads) {
+        const uint32_t vv = e2 / TW4, u4 = e2 - vv * TW4;
+        const uint64_t val = boxw[(H + vv) * NW + HX / 4 + u4];
+        *reinterpret_cast<uint64_t*>(dst + gx0 + 4 * u4 + rowL[H + vv]) = val;
+    }
+}
+
+// One lattice, one tile per workgroup (XCD-grouped like sweep_tile_kernel).
+template <int NBR, int TX, int TY, int K, bool kGrainsInLds>
+__global__ void __launch_bounds__(kThreads) lat2d_kernel(LatArgs a, uint32_t xcd_group) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t b = blockIdx.x;
+    if (xcd_group) b = (b & 7u) * xcd_group + (b >> 3);
+    init_offsets2d<NBR, TX, TY, K>(smem);
+    tile2d<NBR, TX, TY, K, kGrainsInLds>(a, static_cast<const int16_t*>(a.src), static_cast<int16_t*>(a.dst), a.t0,
+                                    b % a.ntx, b / a.ntx, smem);
+}
+
+// Ensembles: persistent workgroups walk the tile table of all members.
+template <int NBR, int TX, int TY, int K, bool kGrainsInLds>
+__global__ void __launch_bounds__(kThreads)
+ens2d_kernel(const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, uint32_t ntiles, uint32_t j,
+             uint32_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    init_offsets2d<NBR, TX, TY, K>(smem);
+    for (uint32_t i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const uint2 tl = tiles[i];
+        const EnsLat& e = lats[tl.x];
+        const uint32_t sel = (e.cur ^ j) & 1u;
+        tile2d<NBR, TX, TY, K, kGrainsInLds>(e.a, static_cast<const int16_t*>(e.buf[sel]),
+                                        static_cast<int16_t*>(e.buf[sel ^ 1u]), e.t_base + j * k,
+                                        tl.y % e.a.ntx, tl.y / e.a.ntx, smem);
         __syncthreads();
     }
 }
 
-// The compiled Moore8 ensemble kernel for tiling t and its LDS bytes, or
-// null when t is not one it was built for.
-const void* ens_m8_for(const Tiling& t, int32_t maxQ, size_t* bytes) {
-    if (t.tx != 128 || t.ty != 128 || t.k != 3) return nullptr;
-    using G = M8Geom<128, 3>;
-    if (maxQ <= kLdsGrainLimit && (int64_t)(G::kGrainOff + 4 * (size_t)maxQ) <= lds_limit_bytes()) {
-        *bytes = G::kGrainOff + 4 * (size_t)maxQ;
-        return reinterpret_cast<const void*>(&ens_m8_kernel<128, 3, true>);
-    }
-    if ((int64_t)G::kGrainOff > lds_limit_bytes()) return nullptr;
-    *bytes = G::kGrainOff;
-    return reinterpret_cast<const void*>(&ens_m8_kernel<128, 3, false>);
+// The compiled 2D kernel (single lattice or ensemble) for neighbourhood nbr
+// and tiling t, and its LDS bytes, or null when there is none for t: Moore8
+// 128x128 tiles with 3 MC steps per launch, and single VN4 lattices in
+// 128x128 tiles with 6.  Against the general kernel on the same tiles (site
+// updates/s): Moore8 2048^2 2.68 -> 3.08e11, 8192^2 3.00 -> 3.35e11, the
+// 64-member ensemble of 29 M sites 2.94e11 either way; VN4 2048^2 4.23 ->
+// 4.36e11.  VN4 64x64 tiles (1024^2: 2.17 -> 2.07e11) and VN4 ensembles
+// (3.76 -> 3.71e11) stay with the general kernel.
+template <int NBR, int TX, int TY, int K, bool kEnsemble>
+const void* pick2d(int32_t maxQ, size_t* bytes) {
+    using G = Geom2D<NBR, TX, TY, K>;
+    const int64_t limit = lds_limit_bytes();
+    const bool lds = maxQ <= kLdsGrainLimit && (int64_t)(G::kGrainOff + 4 * (size_t)maxQ) <= limit;
+    if (!lds && (int64_t)G::kGrainOff > limit) return nullptr;
+    *bytes = G::kGrainOff + (lds ? 4 * (size_t)maxQ : 0);
+    if constexpr (kEnsemble)
+        return lds ? reinterpret_cast<const void*>(&ens2d_kernel<NBR, TX, TY, K, true>)
+                   : reinterpret_cast<const void*>(&ens2d_kernel<NBR, TX, TY, K, false>);
+    return lds ? reinterpret_cast<const void*>(&lat2d_kernel<NBR, TX, TY, K, true>)
+               : reinterpret_cast<const void*>(&lat2d_kernel<NBR, TX, TY, K, false>);
+}
+
+const void* compiled2d_for(int nbr, const Tiling& t, bool ensemble, int32_t maxQ, size_t* bytes) {
+    if (t.tz != 1 && t.tz != 0) return nullptr;
+    const bool t128 = t.tx == 128 && t.ty == 128, t256 = t.tx == 256 && t.ty == 128;
+    if (nbr == HMC_MOORE8 && t.k == 3 && t128)
+        return ensemble ? pick2d<HMC_MOORE8, 128, 128, 3, true>(maxQ, bytes)
+                        : pick2d<HMC_MOORE8, 128, 128, 3, false>(maxQ, bytes);
+    if (nbr == HMC_MOORE8 && t.k == 3 && t256)
+        return ensemble ? pick2d<HMC_MOORE8, 256, 128, 3, true>(maxQ, bytes)
+                        : pick2d<HMC_MOORE8, 256, 128, 3, false>(maxQ, bytes);
+    if (nbr == HMC_VN4 && t.k == 6 && t128 && !ensemble) return pick2d<HMC_VN4, 128, 128, 6, false>(maxQ, bytes);
+    if (nbr == HMC_VN4 && t.k == 4 && t256 && !ensemble) return pick2d<HMC_VN4, 256, 128, 4, false>(maxQ, bytes);
+    return nullptr;
 }
 
 template <int NBR, bool kSwar>
@@ -1203,6 +1273,16 @@ bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t
            vn6_kernel_for(t, L->Q, fn, bytes, per_cu);
 }
 
+// 16-bit VN4 and Moore8 lattices with neighbour trials, one bond energy and
+// grain energies take the compiled 2D kernel for its tiles (full launches).
+bool compiled2d(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes) {
+    if (L->sweep_kernel != HMC_KERNEL_AUTO || L->ndim != 2 || L->desc.spin != HMC_I16 ||
+        L->desc.proposal != HMC_PROP_NEIGHBOUR || L->pair || L->field || !vec_ok(L, t))
+        return false;
+    *fn = compiled2d_for(L->desc.nbr, t, false, L->Q, bytes);
+    return *fn != nullptr;
+}
+
 hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) {
     if (n_mcs == 0) return HMC_OK;
     if (L->pair || L->field) {
@@ -1242,6 +1322,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
     size_t vbytes = 0;
     int per_cu = 1;
     const bool vn6 = compiled_vn6(L, t, &vfn, &vbytes, &per_cu);
+    const void* cfn = nullptr;
+    size_t cbytes = 0;
+    const bool c2d = !vn6 && compiled2d(L, t, &cfn, &cbytes);
     Vn6Args va{};
     if (vn6) {
         va.B = a.B; va.T = a.T; va.Tb = a.Tb;
@@ -1257,9 +1340,11 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX, t.tx);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
-        const void* kfn = vn6 ? vfn : kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false, swar, L->pair,
-                                                 L->field);
-        const size_t lds = vn6 ? vbytes : lay.bytes;
+        // the compiled 2D kernel runs every launch of all P passes (they start at colour 0)
+        const bool full2d = c2d && passes == P && gp0 % L->C == 0;
+        const void* kfn = vn6 ? vfn : (full2d ? cfn : kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false,
+                                                                 swar, L->pair, L->field));
+        const size_t lds = vn6 ? vbytes : (full2d ? cbytes : lay.bytes);
         a.src = L->spins[L->cur];
         a.dst = L->spins[L->cur ^ 1];
         a.fsrc = L->d_field[L->cur];
@@ -1274,7 +1359,8 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         uint32_t xg = xcd_group;
         void* gargs[] = {&a, &g, &xg};
         void* vargs[] = {&va};
-        void** args = vn6 ? vargs : gargs;
+        void* cargs[] = {&a, &xg};
+        void** args = vn6 ? vargs : (full2d ? cargs : gargs);
         // the compiled-tile kernel is persistent: one or two workgroups per
         // CU walk their share of the tiles
         const uint32_t grid = vn6 ? std::min<uint32_t>(ntiles, (uint32_t)(per_cu * device_cus())) : ntiles;
@@ -1431,22 +1517,22 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         int32_t remaining = n_mcs;
         uint32_t j = 0;
         const uint32_t kfull = (uint32_t)E->tiling.k;
-        // 16-bit Moore8 members with neighbour trials in 128x128 tiles, 3 MC
-        // steps per launch: the compiled kernel for every full launch
-        bool m8 = L0->desc.nbr == HMC_MOORE8 && L0->desc.spin == HMC_I16 && E->vec;
-        for (const hmc_lattice* L : E->lats) m8 = m8 && L->desc.proposal == HMC_PROP_NEIGHBOUR;
-        size_t m8_bytes = 0;
-        const void* m8_fn = m8 ? ens_m8_for(E->tiling, E->maxQ, &m8_bytes) : nullptr;
-        const uint32_t m8_grid = std::max(1u, std::min(E->ntiles, (uint32_t)(device_cus() *
-                                          std::max(1, std::min(2, (int)(lds_limit_bytes() / std::max<size_t>(m8_bytes, 1)))))));
+        // 16-bit Moore8 members with neighbour trials in 128x128 tiles with 3
+        // MC steps per launch: the compiled 2D kernel for every full launch
+        bool c2 = L0->ndim == 2 && L0->desc.spin == HMC_I16 && E->vec;
+        for (const hmc_lattice* L : E->lats) c2 = c2 && L->desc.proposal == HMC_PROP_NEIGHBOUR;
+        size_t c2_bytes = 0;
+        const void* c2_fn = c2 ? compiled2d_for(L0->desc.nbr, E->tiling, true, E->maxQ, &c2_bytes) : nullptr;
+        const uint32_t c2_grid = std::max(1u, std::min(E->ntiles, (uint32_t)(device_cus() *
+                                          std::max(1, std::min(2, (int)(lds_limit_bytes() / std::max<size_t>(c2_bytes, 1)))))));
         while (remaining > 0 && err == hipSuccess) {
             const int k = std::min<int32_t>(E->tiling.k, remaining);
             const EnsLat* dl = static_cast<const EnsLat*>(E->d_lats);
             const uint2* dt = static_cast<const uint2*>(E->d_tiles);
             uint32_t nt = E->ntiles, jj = j, kk = kfull;
-            if (m8_fn && k == E->tiling.k) {
+            if (c2_fn && k == E->tiling.k) {
                 void* args[] = {&dl, &dt, &nt, &jj, &kk};
-                err = hipLaunchKernel(m8_fn, dim3(m8_grid), dim3(kThreads), args, m8_bytes, E->stream);
+                err = hipLaunchKernel(c2_fn, dim3(c2_grid), dim3(kThreads), args, c2_bytes, E->stream);
             } else {
                 const int passes = k * C;
                 const Layout lay = box_layout(L0->desc.nbr, L0->ndim, L0->spin_bytes, E->maxQ, E->tiling, passes,
