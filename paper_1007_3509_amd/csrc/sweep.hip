@@ -870,9 +870,12 @@ __global__ void __launch_bounds__(kThreads) lat2d_kernel(LatArgs a, uint32_t xcd
                                     b % a.ntx, b / a.ntx, smem);
 }
 
-// Ensembles: persistent workgroups walk the tile table of all members.
+// Ensembles: persistent workgroups walk the tile table of all members.  Built
+// for eight waves per SIMD (scalar registers held under 100, a few of them
+// kept in vector lanes) so that two workgroups share a CU whenever their LDS
+// fits: one issues while the other waits at a barrier or on LDS.
 template <int NBR, int TX, int TY, int K, bool kGrainsInLds>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 ens2d_kernel(const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, uint32_t ntiles, uint32_t j,
              uint32_t k) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -900,7 +903,11 @@ template <int NBR, int TX, int TY, int K, bool kEnsemble>
 const void* pick2d(int32_t maxQ, size_t* bytes) {
     using G = Geom2D<NBR, TX, TY, K>;
     const int64_t limit = lds_limit_bytes();
-    const bool lds = maxQ <= kLdsGrainLimit && (int64_t)(G::kGrainOff + 4 * (size_t)maxQ) <= limit;
+    // ensembles keep the grain energies in LDS only while two workgroups
+    // still fit a CU (64 Moore8 members up to 2000 grains: 2.94 -> 3.82e11
+    // site updates/s with them read through the caches instead)
+    const int64_t fit = kEnsemble && 2 * (int64_t)G::kGrainOff <= limit ? limit / 2 : limit;
+    const bool lds = maxQ <= kLdsGrainLimit && (int64_t)(G::kGrainOff + 4 * (size_t)maxQ) <= fit;
     if (!lds && (int64_t)G::kGrainOff > limit) return nullptr;
     *bytes = G::kGrainOff + (lds ? 4 * (size_t)maxQ : 0);
     if constexpr (kEnsemble)
