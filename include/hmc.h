@@ -257,10 +257,11 @@ hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
  * their tile where there is one: six-neighbour 64x16x16, 32x32x16,
  * 32x16x16, 16x16x16 or 64x16x8 with one or two colour passes per launch
  * (32x16x16, the default tile of such lattices, 16x16x16 and 64x16x8 run two
- * workgroups per CU); four-neighbour 128x128 with 6 MC steps per launch,
- * eight-neighbour 128x128 with 3 (launches of fewer passes, at the end of a
- * call, take the general kernel); everything else the general tile kernel.  HMC_KERNEL_GENERIC: always the general kernel.  The spins do not
- * depend on the choice.  Errors: INVAL. */
+ * workgroups per CU); four-neighbour 128x128 with 6 MC steps per launch
+ * and 256x128 with 4; eight-neighbour 128x128 and 256x128 with 3 (launches
+ * of fewer passes, at the end of a call, take the general kernel);
+ * everything else the general tile kernel.  HMC_KERNEL_GENERIC: always the
+ * general kernel.  The spins do not depend on the choice.  Errors: INVAL. */
 enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1, HMC_KERNEL_COMPILED = 2 };
 hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);
 /* The kernel the next full sweep launch of L will run: HMC_KERNEL_COMPILED
