@@ -270,7 +270,7 @@ def main():
     achieved = su_per_launch * bytes_per_su / avg_launch_s / 1e9
     tiling = lat.tiling()
     if hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED:
-        kname = "vn6_tile_kernel" if len(w.dims) == 3 else "lat2d_kernel"
+        kname = "lat26_kernel" if w.nbr == hmc.HMC_MOORE26 else ("vn6_tile_kernel" if len(w.dims) == 3 else "lat2d_kernel")
     else:
         kname = "sweep_tile_kernel"
     prof = measured_profile(w.name, tiling, kernel=kname)

@@ -260,7 +260,9 @@ hmc_status hmc_get_tiling(const hmc_lattice *L, int32_t *out4);
  * workgroups per CU); four-neighbour 128x128 with 6 MC steps per launch
  * and 256x128 with 4; eight-neighbour 128x128 and 256x128 with 3 (launches
  * of fewer passes, at the end of a call, take the general kernel);
- * everything else the general tile kernel.  HMC_KERNEL_GENERIC: always the
+ * 26-neighbour 32x16x16 with two or four colour passes per launch (two, the
+ * default of such lattices when their sides allow the tile); everything else
+ * the general tile kernel.  HMC_KERNEL_GENERIC: always the
  * general kernel.  The spins do not depend on the choice.  Errors: INVAL. */
 enum { HMC_KERNEL_AUTO = 0, HMC_KERNEL_GENERIC = 1, HMC_KERNEL_COMPILED = 2 };
 hmc_status hmc_set_sweep_kernel(hmc_lattice *L, int32_t which);

@@ -333,6 +333,7 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
 bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes, int* per_cu);
 bool compiled_vn6_model(const hmc_lattice* L);
 bool compiled2d(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes);
+bool compiled_moore26_model(const hmc_lattice* L);
 hmc_status launch_voronoi(hmc_lattice* L, uint64_t vseed);
 hmc_status launch_boundary_count(hmc_lattice* L);
 hmc_status launch_histogram(hmc_lattice* L);   // fills L->d_areas

@@ -891,6 +891,233 @@ ens2d_kernel(const EnsLat* __restrict__ lats, const uint2* __restrict__ tiles, u
     }
 }
 
+// ----------------------------------------------------------------------
+// 16-bit Moore26 lattices (eight colours) in TX x TY x TZ tiles, P colour
+// passes per launch starting at any colour, neighbour trials: the method,
+// random numbers and integer acceptance of process_tile with the box
+// geometry and the 26 neighbour offsets fixed at compile time.  A pass walks
+// the box rows of its (y, z) parity in 4-site words from a fixed word column
+// per thread; a word is compared with the nine rows around it, each also
+// shifted one site each way, and its two fields of the pass's x parity are
+// queued when a neighbour differs.  One tile per workgroup.
+
+template <int TX, int TY, int TZ, int P>
+struct Geom26 {
+    static constexpr int M = 26, C = 8, H = P, HX = (P + 3) & ~3;
+    static constexpr int BX = TX + 2 * HX, BY = TY + 2 * H, BZ = TZ + 2 * H, BXY = BX * BY, NBOX = BXY * BZ;
+    static constexpr int NW = BX / 4, NROWS = BY * BZ, NWORDS = NW * NROWS;
+    static constexpr int PRE = (NWORDS + kThreads - 1) / kThreads;
+    // the colour class of the first (largest) pass region: an eighth of it
+    static constexpr int QCAP = (BX - 2 * (1 + HX - H)) * (BY - 2) * (BZ - 2) / C + 1;
+    static constexpr size_t kBoundOff = 0;                                  // uint32[2 * kBoundPairs]
+    static constexpr size_t kCountOff = 8 * (size_t)kBoundPairs;            // uint32[2]
+    static constexpr size_t kOffsetOff = kCountOff + 16;                    // int32[26]: neighbour offsets
+    static constexpr size_t kGxOff = kOffsetOff + 128;                      // uint32[BX]
+    static constexpr size_t kRowOff = kGxOff + align16(4 * (size_t)BX);     // uint32[NROWS]
+    static constexpr size_t kBoxOff = kRowOff + align16(4 * (size_t)NROWS); // int16[NBOX]
+    static constexpr size_t kQueueOff = kBoxOff + align16(2 * (size_t)NBOX);
+    static constexpr size_t kGrainOff = kQueueOff + align16(4 * (size_t)QCAP);   // int32[Q] (grains in LDS)
+    static_assert(TX % 4 == 0 && HX >= H && P <= 8, "tile and halo");
+    static_assert(NBOX < 65536 && NROWS < 65536, "queue entries pack the box index and row in 16 bits each");
+};
+
+template <int TX, int TY, int TZ, int P, bool kGrainsInLds>
+__global__ void __launch_bounds__(kThreads) lat26_kernel(LatArgs a, uint32_t xcd_group) {
+    using G = Geom26<TX, TY, TZ, P>;
+    constexpr int BX = G::BX, BY = G::BY, BXY = G::BXY, NW = G::NW, H = G::H, HX = G::HX;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* tbound = reinterpret_cast<uint32_t*>(smem + G::kBoundOff);
+    uint32_t* qcount = reinterpret_cast<uint32_t*>(smem + G::kCountOff);
+    int32_t* noff = reinterpret_cast<int32_t*>(smem + G::kOffsetOff);
+    uint32_t* gx = reinterpret_cast<uint32_t*>(smem + G::kGxOff);
+    uint32_t* rowL = reinterpret_cast<uint32_t*>(smem + G::kRowOff);
+    int16_t* box = reinterpret_cast<int16_t*>(smem + G::kBoxOff);
+    uint64_t* boxw = reinterpret_cast<uint64_t*>(smem + G::kBoxOff);
+    uint32_t* queue = reinterpret_cast<uint32_t*>(smem + G::kQueueOff);
+    int32_t* sB = reinterpret_cast<int32_t*>(smem + G::kGrainOff);
+    const int16_t* __restrict__ src = static_cast<const int16_t*>(a.src);
+    int16_t* __restrict__ dst = static_cast<int16_t*>(a.dst);
+    const int32_t* __restrict__ Bq = kGrainsInLds ? sB : a.B;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    uint32_t b = blockIdx.x;
+    if (xcd_group) b = (b & 7u) * xcd_group + (b >> 3);
+    const uint32_t tx = b % a.ntx, ty = (b / a.ntx) % a.nty, tz = b / (a.ntx * a.nty);
+    const int32_t x0 = (int32_t)(tx * TX) - HX, y0 = (int32_t)(ty * TY) - H, z0 = (int32_t)(tz * TZ) - H;
+
+    if (tid < 26u) {   // box offset of neighbour k in the trial order
+        const int k = (int)tid;
+        noff[tid] = nbr_dx(HMC_MOORE26, k) + nbr_dy(HMC_MOORE26, k) * BX + nbr_dz(HMC_MOORE26, k) * BXY;
+    }
+    for (uint32_t u = tid; u < (uint32_t)BX; u += kThreads) gx[u] = wrap_coord(x0 + (int32_t)u, a.Lx);
+    for (uint32_t r = tid; r < (uint32_t)G::NROWS; r += kThreads) {
+        const uint32_t v = r % BY, w = r / BY;
+        rowL[r] = a.Lx * (wrap_coord(y0 + (int32_t)v, a.Ly) + a.Ly * wrap_coord(z0 + (int32_t)w, a.Lz));
+    }
+    for (uint32_t r = tid; r < 2u * (uint32_t)a.nbound; r += kThreads) tbound[r] = a.Tb[r];
+    if constexpr (kGrainsInLds)
+        for (uint32_t q = tid; q < (uint32_t)a.Q; q += kThreads) sB[q] = a.B[q];
+    if (tid < 2) qcount[tid] = 0;
+    __syncthreads();
+    {   // the box, four spins per 8-byte access (rows start at a multiple of 4)
+        uint64_t wv[G::PRE];
+#pragma unroll
+        for (int q = 0; q < G::PRE; ++q) {
+            const uint32_t e2 = tid + (uint32_t)q * kThreads;
+            const uint32_t ec = e2 < (uint32_t)G::NWORDS ? e2 : 0u;
+            const uint32_t r = ec / NW, u4 = ec - r * NW;
+            wv[q] = *reinterpret_cast<const uint64_t*>(src + gx[4 * u4] + rowL[r]);
+        }
+#pragma unroll
+        for (int q = 0; q < G::PRE; ++q) {
+            const uint32_t e2 = tid + (uint32_t)q * kThreads;
+            if (e2 < (uint32_t)G::NWORDS) boxw[e2] = wv[q];
+        }
+    }
+    __syncthreads();
+
+    // colour parity of box column, row and plane 0
+    const uint32_t px = (uint32_t)x0 & 1u, py = (uint32_t)y0 & 1u, pz = (uint32_t)z0 & 1u;
+    unsigned long long drawn = 0;
+    for (int p = 0; p < P; ++p) {
+        const uint32_t gp = a.c0 + (uint32_t)p;   // pass counted from colour 0 of MC step t0
+        const uint32_t c = gp & 7u, t = a.t0 + (gp >> 3);
+        const uint32_t cx = c & 1u, cy = (c >> 1) & 1u, cz = c >> 2;
+        const uint32_t R = (uint32_t)p + 1u;           // ring: the pass region is R sites inside the box
+        const uint32_t lox = R + (uint32_t)(HX - H);
+        const uint32_t s_lo = lox >> 2, s_hi = ((uint32_t)BX - lox - 1u) >> 2, nseg = s_hi - s_lo + 1u;
+        // rows of the pass's y and z parity
+        const uint32_t ny = ((uint32_t)BY - 2u * R) / 2u, nz = ((uint32_t)G::BZ - 2u * R) / 2u, nrows = ny * nz;
+        const uint32_t m_ny = magic(ny);
+        const uint32_t vpar = (cy ^ (R + py)) & 1u, wpar = (cz ^ (R + pz)) & 1u;
+        const uint32_t rpi = kThreads / nseg;
+        const uint32_t sg = s_lo + tid % nseg, i0 = tid / nseg;
+        const bool tact = tid < rpi * nseg;
+        const uint32_t u0 = 4 * sg;
+        const uint32_t kf = (cx ^ px) & 1u;   // first field of the pass's x parity in a word
+        // a field of that parity has one x neighbour outside the word: before
+        // it (first field 0) or after it (first field 1)
+        const uint32_t ue = kf ? (u0 + 4 < (uint32_t)BX ? u0 + 4 : (uint32_t)BX - 1) : (sg > 0 ? u0 - 1 : 0u);
+        const uint32_t ua = u0 + kf;
+        const bool oka = ua >= lox && ua < (uint32_t)BX - lox, okb = ua + 2 >= lox && ua + 2 < (uint32_t)BX - lox;
+        uint32_t* qc = &qcount[p & 1];
+        const uint32_t iters = (nrows + rpi - 1) / rpi;
+        for (uint32_t it = 0; it < iters; ++it) {
+            const uint32_t ir = i0 + it * rpi;
+            bool pa = false, pb = false;
+            uint32_t ea = 0;
+            if (tact && ir < nrows) {
+                const uint32_t iz = fdiv(ir, m_ny), iy = ir - iz * ny;
+                const uint32_t row = (R + 2 * iy + vpar) + (uint32_t)BY * (R + 2 * iz + wpar);
+                const uint32_t wi = row * NW + sg;
+                const uint64_t S = boxw[wi];
+                const uint32_t sl = (uint32_t)S, sh = (uint32_t)(S >> 32);
+                uint32_t fl = 0, fh = 0;
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const bool centre = dy == 0 && dz == 0;
+                        const int dr = dy + dz * BY;
+                        const uint64_t W = centre ? S : boxw[(int)wi + dr * NW];
+                        const uint32_t ev = (uint16_t)box[((int)row + dr) * BX + (int)ue];
+                        const uint32_t wl = (uint32_t)W, wh = (uint32_t)(W >> 32);
+                        const uint32_t mid = __builtin_amdgcn_alignbit(wh, wl, 16);   // sites 1, 2
+                        fl |= (sl ^ ((wl << 16) | ev)) | (sl ^ mid);
+                        fh |= (sh ^ mid) | (sh ^ __builtin_amdgcn_alignbit(ev, wh, 16));
+                        if (!centre) {
+                            fl |= sl ^ wl;
+                            fh |= sh ^ wh;
+                        }
+                    }
+                }
+                pa = oka && __builtin_amdgcn_ubfe(fl, 16 * kf, 16) != 0;
+                pb = okb && __builtin_amdgcn_ubfe(fh, 16 * kf, 16) != 0;
+                ea = (row * BX + ua) | (row << 16);
+            }
+            const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+            const uint32_t na = (uint32_t)__popcll(ma);
+            const uint32_t n = na + (uint32_t)__popcll(mb);
+            if (n) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(qc, n);
+                base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                if (pa) queue[base + (uint32_t)__popcll(ma & lanes_below)] = ea;
+                if (pb) queue[base + na + (uint32_t)__popcll(mb & lanes_below)] = ea + 2;
+            }
+        }
+        __syncthreads();
+        const uint32_t count = *qc;
+        if (tid == 0) {
+            qcount[(p + 1) & 1] = 0;
+            drawn += count;
+        }
+        auto trial = [&](uint32_t en) __attribute__((always_inline)) {
+            const uint32_t idx = en & 0xFFFFu, row = en >> 16;
+            const uint32_t u = idx - row * BX;
+            const int32_t q = box[idx];
+            int32_t nb[26];
+#pragma unroll
+            for (int k = 0; k < 26; ++k)
+                nb[k] = box[(int)idx + nbr_dx(HMC_MOORE26, k) + nbr_dy(HMC_MOORE26, k) * BX +
+                            nbr_dz(HMC_MOORE26, k) * BXY];
+            const uint32_t site = gx[u] + rowL[row];
+            const bool q_ok = (uint32_t)q < (uint32_t)a.Q;   // a value outside [0, Q) never moves
+            const int32_t bq = Bq[q_ok ? q : 0];
+            const Philox2 r = philox_r01(site, t, c, 0u, a.k0, a.k1);
+            const uint32_t kk = __umulhi(r.r0, 26u);
+            const int32_t qn = box[(int32_t)idx + noff[kk]];
+            if (!q_ok || qn == q || (uint32_t)qn >= (uint32_t)a.Q) return;
+            const int32_t dn = like_difference16<26>(nb, q, qn);
+            const int32_t dB = Bq[qn] - bq;
+            const int32_t d = a.J_fx * dn + dB;
+            bool accept = d <= 0;
+            if (!accept) {
+                // T is non-increasing in d: the bucket's bounds decide almost every trial
+                const int rowT = dn - a.dn_lo;
+                const uint32_t col = (uint32_t)(dB + a.R);
+                const uint32_t bucket = a.m_bw ? __umulhi(col, a.m_bw) : col / a.bw;
+                const uint32_t bk = (uint32_t)rowT * (uint32_t)a.nb + bucket;
+                if (r.r1 < tbound[2 * bk]) accept = true;
+                else if (r.r1 < tbound[2 * bk + 1]) accept = r.r1 < a.T[rowT * a.TW + (int)col];
+            }
+            if (accept) box[idx] = (int16_t)qn;
+        };
+        for (uint32_t e0 = tid; e0 < count; e0 += 2 * kThreads) {
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+                const uint32_t en = e0 + q2 * kThreads;
+                if (en < count) trial(queue[en]);
+            }
+        }
+        __syncthreads();
+    }
+    if (a.trials && tid == 0) atomicAdd(&a.trials[blockIdx.x & (kTrialSlots - 1)], drawn);
+    // the tile back to global memory, 8-byte words
+    constexpr int TW4 = TX / 4;
+    const uint32_t gx0 = gx[HX];
+    for (uint32_t e2 = tid; e2 < (uint32_t)(TW4 * TY * TZ); e2 += kThreads) {
+        const uint32_t u4 = e2 % TW4, rr = e2 / TW4;
+        const uint32_t vv = rr % TY, ww = rr / TY;
+        const uint32_t brow = (H + vv) + BY * (H + ww);
+        const uint64_t val = boxw[brow * NW + HX / 4 + u4];
+        *reinterpret_cast<uint64_t*>(dst + gx0 + 4 * u4 + rowL[brow]) = val;
+    }
+}
+
+template <int TX, int TY, int TZ, int P>
+const void* pick26(int32_t maxQ, size_t* bytes) {
+    using G = Geom26<TX, TY, TZ, P>;
+    const int64_t limit = lds_limit_bytes();
+    const bool lds = maxQ <= kLdsGrainLimit && (int64_t)(G::kGrainOff + 4 * (size_t)maxQ) <= limit;
+    if (!lds && (int64_t)G::kGrainOff > limit) return nullptr;
+    *bytes = G::kGrainOff + (lds ? 4 * (size_t)maxQ : 0);
+    return lds ? reinterpret_cast<const void*>(&lat26_kernel<TX, TY, TZ, P, true>)
+               : reinterpret_cast<const void*>(&lat26_kernel<TX, TY, TZ, P, false>);
+}
+
 // The compiled 2D kernel (single lattice or ensemble) for neighbourhood nbr
 // and tiling t, and its LDS bytes, or null when there is none for t: Moore8
 // 128x128 tiles with 3 MC steps per launch, and single VN4 lattices in
@@ -918,6 +1145,12 @@ const void* pick2d(int32_t maxQ, size_t* bytes) {
 }
 
 const void* compiled2d_for(int nbr, const Tiling& t, bool ensemble, int32_t maxQ, size_t* bytes) {
+    if (nbr == HMC_MOORE26) {   // single lattices, 32x16x16 tiles, two or four colour passes
+        if (ensemble || t.tx != 32 || t.ty != 16 || t.tz != 16) return nullptr;
+        if (t.k == -2) return pick26<32, 16, 16, 2>(maxQ, bytes);
+        if (t.k == -4) return pick26<32, 16, 16, 4>(maxQ, bytes);
+        return nullptr;
+    }
     if (t.tz != 1 && t.tz != 0) return nullptr;
     const bool t128 = t.tx == 128 && t.ty == 128, t256 = t.tx == 256 && t.ty == 128;
     if (nbr == HMC_MOORE8 && t.k == 3 && t128)
@@ -1236,6 +1469,14 @@ hmc_status choose_tiling(const hmc_lattice* L, Tiling& t, bool explicit_request)
                 v.tx = 32; v.ty = 16; v.tz = 16; v.k = 1;
                 cands.push_back(v);
             }
+            // the compiled Moore26 kernel is fastest with two colour passes
+            // per launch (128^3: 4.41e10 site updates/s; four passes 4.29e10,
+            // the general kernel 3.93e10 with four and 3.60e10 with two)
+            if (compiled_moore26_model(L) && dims[0] % 32 == 0 && dims[1] % 16 == 0 && dims[2] % 16 == 0) {
+                Tiling v;
+                v.tx = 32; v.ty = 16; v.tz = 16; v.k = -2;
+                cands.push_back(v);
+            }
             for (const Tiling& d : default_tilings(L->desc.nbr)) cands.push_back(d);
             for (const Tiling& d : cands) {
                 r = req;
@@ -1280,10 +1521,16 @@ bool compiled_vn6(const hmc_lattice* L, const Tiling& t, const void** fn, size_t
            vn6_kernel_for(t, L->Q, fn, bytes, per_cu);
 }
 
-// 16-bit VN4 and Moore8 lattices with neighbour trials, one bond energy and
-// grain energies take the compiled 2D kernel for its tiles (full launches).
+bool compiled_moore26_model(const hmc_lattice* L) {
+    return L->sweep_kernel == HMC_KERNEL_AUTO && L->desc.nbr == HMC_MOORE26 && L->desc.spin == HMC_I16 &&
+           L->desc.proposal == HMC_PROP_NEIGHBOUR && !L->pair && !L->field && L->desc.dims[0] % 4 == 0;
+}
+
+// 16-bit VN4, Moore8 and Moore26 lattices with neighbour trials, one bond
+// energy and grain energies take the compiled kernel for their tile (full
+// launches).
 bool compiled2d(const hmc_lattice* L, const Tiling& t, const void** fn, size_t* bytes) {
-    if (L->sweep_kernel != HMC_KERNEL_AUTO || L->ndim != 2 || L->desc.spin != HMC_I16 ||
+    if (L->sweep_kernel != HMC_KERNEL_AUTO || (L->ndim != 2 && L->desc.nbr != HMC_MOORE26) || L->desc.spin != HMC_I16 ||
         L->desc.proposal != HMC_PROP_NEIGHBOUR || L->pair || L->field || !vec_ok(L, t))
         return false;
     *fn = compiled2d_for(L->desc.nbr, t, false, L->Q, bytes);
@@ -1347,8 +1594,9 @@ hmc_status launch_sweep(hmc_lattice* L, float kT, int32_t n_mcs, uint64_t seed) 
         const Layout lay = box_layout(L, t, passes);
         const bool swar = use_swar(L->desc.nbr, L->desc.spin, lay.BX, t.tx);
         RunArgs g = run_args(lay, L->desc.nbr, t, passes, swar);
-        // the compiled 2D kernel runs every launch of all P passes (they start at colour 0)
-        const bool full2d = c2d && passes == P && gp0 % L->C == 0;
+        // the compiled tile kernel runs every launch of all P passes (the 2D
+        // ones start at colour 0; the Moore26 one takes the launch's colour)
+        const bool full2d = c2d && passes == P && (L->desc.nbr == HMC_MOORE26 || gp0 % L->C == 0);
         const void* kfn = vn6 ? vfn : (full2d ? cfn : kernel_ptr(L->desc.nbr, L->desc.spin, lay.grains_in_lds, false,
                                                                  swar, L->pair, L->field));
         const size_t lds = vn6 ? vbytes : (full2d ? cbytes : lay.bytes);

@@ -38,7 +38,7 @@ def _fields(path):
 
 @pytest.mark.parametrize("workload", sorted(SWEEP))
 def test_sweep_profiles_are_machine_readable(workload):
-    kernel = "lat2d_kernel" if workload == "stress_2d_16384" else "sweep_tile_kernel"
+    kernel = {"stress_2d_16384": "lat2d_kernel", "moore26_3d_128": "lat26_kernel"}.get(workload, "sweep_tile_kernel")
     f = _fields(os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md"))
     assert re.fullmatch(r"[0-9a-f]{64}", f["kernel_source_sha256"])
     assert float(f["traffic_bytes_per_launch"]) > 0 and float(f["valu_wave_instructions_per_launch"]) > 0

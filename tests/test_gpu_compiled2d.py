@@ -1,7 +1,8 @@
-"""GPU: the 2D sweep kernel with compile-time tiles (16-bit VN4 in 128x128
-tiles with 6 MC steps per launch and 256x128 with 4, Moore8 in 128x128 and
-256x128 tiles with 3) against the general tile kernel and the oracle,
-element by element (Sec. 3 trials, Sec. 4 Red/Black passes).
+"""GPU: the sweep kernels with compile-time tiles for 16-bit lattices other
+than the six-neighbour one (VN4 in 128x128 tiles with 6 MC steps per launch
+and 256x128 with 4, Moore8 in 128x128 and 256x128 tiles with 3, Moore26 in
+32x16x16 tiles with 2 or 4 colour passes) against the general tile kernel and the
+oracle, element by element (Sec. 3 trials, Sec. 4 Red/Black passes).
 
 * single lattices of several tiles along both axes, grains in LDS (Q <=
   4096) and in global memory, MC step counts that end in a shorter launch
@@ -56,7 +57,10 @@ CASES = [(hmc.HMC_VN4, (384, 256), (128, 128, 1, 6), [6, 9]),
          (hmc.HMC_VN4, (256, 512), (128, 128, 1, 6), [6, 4]),
          (hmc.HMC_VN4, (512, 384), (256, 128, 1, 4), [4, 5]),
          (hmc.HMC_MOORE8, (384, 256), (128, 128, 1, 3), [3, 4]),
-         (hmc.HMC_MOORE8, (768, 256), (256, 128, 1, 3), [6, 2])]
+         (hmc.HMC_MOORE8, (768, 256), (256, 128, 1, 3), [6, 2]),
+         (hmc.HMC_MOORE26, (64, 32, 48), (32, 16, 16, -4), [1, 2]),
+         (hmc.HMC_MOORE26, (64, 32, 48), (32, 16, 16, -2), [2, 1]),
+         (hmc.HMC_MOORE26, (32, 16, 16), (32, 16, 16, -2), [3])]
 
 
 @pytest.mark.parametrize("nbr,dims,tiling,chunks", CASES)
@@ -113,6 +117,34 @@ def test_wrapped_buffer_and_inert_values(nbr, tiling):
         assert np.all(got[100:104, 20:90] == -1) and got[0, 0] == 300
 
 
+@pytest.mark.parametrize("passes", [2, 4])
+def test_moore26_wrapped_buffer_and_inert_values(passes):
+    """Moore26 launches of two or four colour passes start on any colour
+    they divide."""
+    dims, Q, kT, seed = (64, 32, 32), 40, 0.8, 3
+    s = oracle.voronoi(dims, Q, 9).reshape(dims[2], dims[1], dims[0]).astype(np.int16)
+    s[10:12, 3:20, 5:40] = -1
+    s[0, 0, 0] = 300
+    B = synth.quantise(np.linspace(0.0, 0.2, Q))
+    t = torch.from_numpy(s.copy()).to("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    say(f"[gpu] compiled Moore26 wrapped int16 buffer, {passes} passes per launch")
+    with hmc.Lattice(dims, hmc.HMC_MOORE26, Q, stream=stream, dev_ptr=t.data_ptr(), spin=hmc.HMC_I16) as lat:
+        lat.set_grain_energy(B)
+        lat.set_tiling(32, 16, 16, -passes)
+        assert hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED
+        want = s.astype(np.int32)
+        done = 0
+        for n in (1, 2):
+            lat.sweep(kT, n, seed)
+            want = oracle.sweep(want, hmc.HMC_MOORE26, dims, B, kT, n, seed, mcs0=done, threads=THREADS)
+            done += n
+            torch.cuda.synchronize()
+            got = t.cpu().numpy().astype(np.int32)
+            assert np.array_equal(got, want), f"after {done} steps {int(np.sum(got != want))} sites differ"
+        assert np.all(got[10:12, 3:20, 5:40] == -1) and got[0, 0, 0] == 300
+
+
 @pytest.mark.parametrize("nbr,side,tiling", [(hmc.HMC_VN4, 2048, (128, 128, 1, 6)),
                                              (hmc.HMC_MOORE8, 2048, (128, 128, 1, 3)),
                                              (hmc.HMC_VN4, 4096, (256, 128, 1, 4)),
@@ -123,3 +155,10 @@ def test_default_tiling_of_large_lattices_takes_the_compiled_kernel(nbr, side, t
         assert hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED
     with hmc.Lattice((1024, 1024), hmc.HMC_VN4, 4000, spin=hmc.HMC_I16) as lat:
         assert hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_GENERIC
+
+
+def test_moore26_default_tiling_takes_the_compiled_kernel():
+    w = synth.moore26_3d_128()
+    with hmc.Lattice(w.dims, w.nbr, w.n_grains, spin=w.spin) as lat:
+        assert tuple(hmc.hmc_get_tiling(lat.h)) == (32, 16, 16, -2)
+        assert hmc.hmc_get_sweep_kernel(lat.h) == hmc.HMC_KERNEL_COMPILED
