@@ -142,15 +142,21 @@ boundary_kernel(const Spin* __restrict__ s, uint32_t Lx, uint32_t Ly, uint32_t L
         const uint64_t i = b + (threadIdx.x & 63u);
         bool hit = false;
         if (i < N) {
-            const uint32_t x = (uint32_t)(i % Lx), y = (uint32_t)((i / Lx) % Ly), z = (uint32_t)(i / ((uint64_t)Lx * Ly));
-            const int32_t q = (int32_t)s[i];
+            // 32-bit coordinates: a lattice has fewer than 2^32 sites
+            const uint32_t ii = (uint32_t)i, yz = ii / Lx;
+            const uint32_t x = ii - yz * Lx, z = yz / Ly, y = yz - z * Ly;
+            const int32_t q = (int32_t)s[ii];
+            // one step along an axis, periodic
+            auto step = [](uint32_t c, int d, uint32_t L) -> uint32_t {
+                return d > 0 ? (c + 1 == L ? 0u : c + 1) : (d < 0 ? (c == 0 ? L - 1 : c - 1) : c);
+            };
             if ((uint32_t)q < Q) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
-                    const uint32_t xn = (x + Lx + (uint32_t)nbr_dx(NBR, k)) % Lx;
-                    const uint32_t yn = (y + Ly + (uint32_t)nbr_dy(NBR, k)) % Ly;
-                    const uint32_t zn = (z + Lz + (uint32_t)nbr_dz(NBR, k)) % Lz;
-                    hit |= (int32_t)s[xn + (uint64_t)Lx * (yn + (uint64_t)Ly * zn)] != q;
+                    const uint32_t xn = step(x, nbr_dx(NBR, k), Lx);
+                    const uint32_t yn = step(y, nbr_dy(NBR, k), Ly);
+                    const uint32_t zn = step(z, nbr_dz(NBR, k), Lz);
+                    hit |= (int32_t)s[xn + Lx * (yn + Ly * zn)] != q;
                 }
             }
         }
