@@ -128,7 +128,11 @@ hmc_status hmc_lattice_free(hmc_lattice *L);
 
 /* Per-grain bulk energy b(q) of Eq. (7) in 2^-16 units (Sec. 6: carried by
  * the grain).  B_fx: int32[n_grains], host memory (on_device = 0) or device
- * memory (on_device = 1); copied.  n_grains must equal the lattice's Q.
+ * memory (on_device = 1, read after the work queued on the lattice's stream);
+ * copied, so the caller may reuse it on return.  The upload is queued on the
+ * lattice's stream: sweeps queued before the call use the old energies, later
+ * ones the new, and a host array is not held up by the sweeps still running.
+ * n_grains must equal the lattice's Q.
  * Errors: INVAL; RANGE if |J_fx|*M + 2 max|B| >= 2^31. */
 hmc_status hmc_set_grain_energy(hmc_lattice *L, const int32_t *B_fx, int32_t n_grains, int32_t on_device);
 

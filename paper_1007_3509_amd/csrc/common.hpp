@@ -160,9 +160,18 @@ __host__ __device__ constexpr int nbr_dz(int nbr, int k) {
 // decided by the bucket's two numbers alone; kBoundPairs bounds the count.
 constexpr int kBoundPairs = 512;
 struct Table {
-    uint32_t* dev = nullptr;      // rows * TW entries
+    uint32_t* dev = nullptr;      // rows * TW entries (the current slot)
     uint32_t* bounds = nullptr;   // 2 * rows * nb entries
     size_t bytes = 0;             // allocation behind dev (bounds included)
+    // two device slots, each filled from its own pinned staging buffer: a
+    // new table goes to the slot the queued sweeps do not read, in stream
+    // order, without the host waiting for them
+    uint32_t* slot_dev[2] = {nullptr, nullptr};
+    size_t slot_bytes[2] = {0, 0};
+    uint32_t* pin[2] = {nullptr, nullptr};
+    size_t pin_bytes[2] = {0, 0};
+    hipEvent_t uploaded[2] = {nullptr, nullptr};
+    int slot = 0;
     int32_t dn_lo = 0, rows = 0, R = 0, TW = 1;
     int32_t nb = 1, bw = 1;       // buckets per row, columns per bucket
     uint32_t kT_bits = 0;
@@ -242,6 +251,9 @@ struct hmc_lattice_s {
 
     int32_t* dB = nullptr;
     std::vector<int32_t> hB;
+    // pinned staging of grain-energy uploads (stream-ordered, no host wait)
+    int32_t* hB_pinned = nullptr;
+    hipEvent_t hB_uploaded = nullptr;
     int32_t Bmin = 0, Bmax = 0;
     hmc::Table table;
 

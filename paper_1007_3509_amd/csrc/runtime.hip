@@ -146,18 +146,39 @@ hmc_status build_table(Table& tab, float kT, int M, int32_t J_fx, int32_t Bmin, 
     HMC_TRY(table_host(kT, M, J_fx, Bmin, Bmax, lay, host));
     const size_t entries = (size_t)lay.rows * (size_t)lay.TW;
     const size_t bytes = host.size() * sizeof(uint32_t);
-    if (tab.bytes < bytes) {
-        free_table(tab);
+    // the slot the sweeps queued since the last build do not read; the
+    // sweeps that read it were queued before that build, earlier in the stream
+    const int s = tab.valid ? tab.slot ^ 1 : tab.slot;
+    if (!tab.uploaded[s]) HMC_HIP(hipEventCreateWithFlags(&tab.uploaded[s], hipEventDisableTiming));
+    HMC_HIP(hipEventSynchronize(tab.uploaded[s]));   // the last upload from this slot's staging
+    if (tab.slot_bytes[s] < bytes) {
+        HMC_HIP(hipStreamSynchronize(stream));   // growing: nothing queued may still read the old slot
+        dev_free(tab.slot_dev[s], tab.slot_bytes[s]);
+        tab.slot_dev[s] = nullptr;
+        tab.slot_bytes[s] = 0;
         void* p = nullptr;
         HMC_TRY(dev_alloc(&p, bytes, "threshold table"));
-        tab.dev = static_cast<uint32_t*>(p);
-        tab.bytes = bytes;
+        tab.slot_dev[s] = static_cast<uint32_t*>(p);
+        tab.slot_bytes[s] = bytes;
     }
+    if (tab.pin_bytes[s] < bytes) {
+        if (tab.pin[s]) (void)hipHostFree(tab.pin[s]);
+        tab.pin[s] = nullptr;
+        tab.pin_bytes[s] = 0;
+        void* p = nullptr;
+        HMC_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        tab.pin[s] = static_cast<uint32_t*>(p);
+        tab.pin_bytes[s] = bytes;
+    }
+    std::memcpy(tab.pin[s], host.data(), bytes);
+    HMC_HIP(hipMemcpyAsync(tab.slot_dev[s], tab.pin[s], bytes, hipMemcpyHostToDevice, stream));
+    HMC_HIP(hipEventRecord(tab.uploaded[s], stream));
+    tab.slot = s;
+    tab.dev = tab.slot_dev[s];
+    tab.bytes = tab.slot_bytes[s];
     tab.bounds = tab.dev + entries;
     tab.nb = lay.nb;
     tab.bw = lay.bw;
-    HMC_HIP(hipMemcpyAsync(tab.dev, host.data(), bytes, hipMemcpyHostToDevice, stream));
-    HMC_HIP(hipStreamSynchronize(stream));
     tab.dn_lo = lay.dn_lo;
     tab.rows = lay.rows;
     tab.R = lay.R;
@@ -198,7 +219,14 @@ hmc_status build_direct_table(hmc_lattice* L, float kT) {
 }
 
 void free_table(Table& tab) {
-    dev_free(tab.dev, tab.bytes);
+    for (int s = 0; s < 2; ++s) {
+        if (tab.uploaded[s]) {
+            (void)hipEventSynchronize(tab.uploaded[s]);
+            (void)hipEventDestroy(tab.uploaded[s]);
+        }
+        dev_free(tab.slot_dev[s], tab.slot_bytes[s]);
+        if (tab.pin[s]) (void)hipHostFree(tab.pin[s]);
+    }
     tab = Table{};
 }
 
@@ -246,6 +274,9 @@ void destroy(hmc_lattice* L) {
     dev_free(L->spins[1], sb);
     dev_free(L->snap, sb);
     dev_free(L->dB, (size_t)L->Q * 4);
+    if (L->hB_uploaded) (void)hipEventSynchronize(L->hB_uploaded);
+    if (L->hB_pinned) (void)hipHostFree(L->hB_pinned);
+    if (L->hB_uploaded) (void)hipEventDestroy(L->hB_uploaded);
     dev_free(L->d_areas, (size_t)L->Q * 4);
     dev_free(L->d_stats, (size_t)(1 + L->stats_bins_cap) * 8);
     dev_free(L->d_gbin, (size_t)L->Q * 4);
@@ -421,8 +452,26 @@ hmc_status hmc_set_grain_energy(hmc_lattice* L, const int32_t* B_fx, int32_t n_g
         hi = std::max(hi, v);
     }
     HMC_TRY(check_energy_range(L, lo, hi, bond_max(L), L->Fmin, L->Fmax));
-    HMC_HIP(hipMemcpyAsync(L->dB, h.data(), (size_t)n_grains * 4, hipMemcpyHostToDevice, L->stream));
-    HMC_HIP(hipStreamSynchronize(L->stream));
+    // Staged through pinned memory: the copy runs in stream order after the
+    // sweeps already queued (which read the old energies) and the host does
+    // not wait for them; only the previous upload from the staging buffer
+    // must have finished before it is overwritten.
+    if (!L->hB_pinned) {
+        void* p = nullptr;
+        HMC_HIP(hipHostMalloc(&p, (size_t)L->Q * 4, hipHostMallocDefault));
+        L->hB_pinned = static_cast<int32_t*>(p);
+        const hipError_t e = hipEventCreateWithFlags(&L->hB_uploaded, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(L->hB_pinned);
+            L->hB_pinned = nullptr;
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
+    } else {
+        HMC_HIP(hipEventSynchronize(L->hB_uploaded));
+    }
+    std::memcpy(L->hB_pinned, h.data(), (size_t)n_grains * 4);
+    HMC_HIP(hipMemcpyAsync(L->dB, L->hB_pinned, (size_t)n_grains * 4, hipMemcpyHostToDevice, L->stream));
+    HMC_HIP(hipEventRecord(L->hB_uploaded, L->stream));
     L->hB.swap(h);
     L->Bmin = lo;
     L->Bmax = hi;

@@ -1732,11 +1732,6 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
     if (!E->prepared) HMC_TRY(ensemble_prepare(E));
     hmc_lattice* L0 = E->lats[0];
     const int C = L0->C;
-    // order after every member's pending work
-    for (hmc_lattice* L : E->lats) {
-        HMC_HIP(hipEventRecord(E->ev, L->stream));
-        HMC_HIP(hipStreamWaitEvent(E->stream, E->ev, 0));
-    }
     std::vector<EnsLat> h(E->lats.size());
     for (size_t i = 0; i < E->lats.size(); ++i) {
         hmc_lattice* L = E->lats[i];
@@ -1748,6 +1743,11 @@ hmc_status launch_ensemble(hmc_ensemble* E, const float* kT, const uint64_t* see
         h[i].buf[1] = L->spins[1];
         h[i].cur = (uint32_t)L->cur;
         h[i].t_base = (uint32_t)L->mcs;
+    }
+    // order after every member's pending work, its table and energy uploads included
+    for (hmc_lattice* L : E->lats) {
+        HMC_HIP(hipEventRecord(E->ev, L->stream));
+        HMC_HIP(hipStreamWaitEvent(E->stream, E->ev, 0));
     }
     // Upload from pinned staging, two slots in turn: the host waits only for
     // the upload made two calls ago from the same slot (long finished in a
