@@ -213,34 +213,59 @@ __global__ void adam_kernel(const float* __restrict__ g, float* __restrict__ the
 }
 
 constexpr int kPredThreads = 256;
+constexpr int kPredLanes = 4;                             // lanes per sample
+constexpr int kPredSamples = kPredThreads / kPredLanes;   // samples per workgroup
+constexpr int kPredUnits = kHid / kPredLanes;             // hidden units per lane
 
+// Workgroups of kPredThreads lanes for n samples.
+inline unsigned predict_blocks(int64_t n) { return (unsigned)((n + kPredSamples - 1) / kPredSamples); }
+
+// Inference, four lanes per sample: each lane forms a quarter of the hidden
+// units of both layers (every unit's sum in the same order as one lane
+// alone would), the first layer is shared through LDS, and the four partial
+// output sums are added in a fixed order.
 __global__ void __launch_bounds__(kPredThreads)
 predict_kernel(const float* __restrict__ theta, const float* __restrict__ X, int64_t n, double mean, double sdev,
                double* __restrict__ E_out, float* __restrict__ y_std_out) {
     __shared__ float W[kNP];
+    __shared__ float H1[kPredSamples][kHid];
     for (int p = threadIdx.x; p < kNP; p += blockDim.x) W[p] = theta[p];
     __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+    const int ls = threadIdx.x / kPredLanes, part = threadIdx.x % kPredLanes;
+    const int64_t s = (int64_t)blockIdx.x * kPredSamples + ls;
+    const bool live = s < n;
     float x[kIn];
-    for (int j = 0; j < kIn; ++j) x[j] = X[s * kIn + j];
-    float h1[kHid];
+    for (int j = 0; j < kIn; ++j) x[j] = live ? X[s * kIn + j] : 0.0f;
 #pragma unroll
-    for (int i = 0; i < kHid; ++i) {
+    for (int q = 0; q < kPredUnits; ++q) {
+        const int i = part * kPredUnits + q;
         float a = W[ob1 + i];
 #pragma unroll
         for (int j = 0; j < kIn; ++j) a += W[oW1 + i * kIn + j] * x[j];
-        h1[i] = tanhf(a);
+        H1[ls][i] = tanhf(a);
     }
-    float y = W[ob3];
-    for (int i = 0; i < kHid; ++i) {
+    // the four lanes of a sample sit in one wave, whose LDS operations run in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float h1[kHid];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) h1[j] = H1[ls][j];
+    float y = 0.0f;
+    for (int q = 0; q < kPredUnits; ++q) {
+        const int i = part * kPredUnits + q;
         float a = W[ob2 + i];
 #pragma unroll
         for (int j = 0; j < kHid; ++j) a += W[oW2 + i * kHid + j] * h1[j];
         y += W[ow3 + i] * tanhf(a);
     }
-    if (y_std_out) y_std_out[s] = y;
-    if (E_out) E_out[s] = (double)y * sdev + mean;
+    // partial sums of lanes 1..3 of the sample to lane 0, added in lane order
+    const float y1 = __shfl_down(y, 1, kPredLanes), y2 = __shfl_down(y, 2, kPredLanes),
+                y3 = __shfl_down(y, 3, kPredLanes);
+    if (!live || part != 0) return;
+    const float out = ((W[ob3] + y) + y1) + (y2 + y3);
+    if (y_std_out) y_std_out[s] = out;
+    if (E_out) E_out[s] = (double)out * sdev + mean;
 }
 
 __global__ void quantise_kernel(const double* __restrict__ E, int32_t n, double scale, int32_t* __restrict__ B) {
@@ -543,7 +568,7 @@ hmc_status hmc_mlp_predict(hmc_mlp* M, const double* euler, const double* eps, i
         HMC_TRY(M->E.ensure((size_t)n * 8, "mlp predictions"));
         dout = M->E.as<double>();
     }
-    predict_kernel<<<(unsigned)((n + kPredThreads - 1) / kPredThreads), kPredThreads, 0, M->stream>>>(
+    predict_kernel<<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
         M->theta.as<float>(), M->X.as<float>(), n, M->mean, M->sdev, dout, nullptr);
     HMC_HIP(hipGetLastError());
     if (!on_device) HMC_HIP(hipMemcpyAsync(E_out, dout, (size_t)n * 8, hipMemcpyDeviceToHost, M->stream));
@@ -558,7 +583,7 @@ hmc_status hmc_mlp_forward(hmc_mlp* M, const float* X, int32_t n, float* y_out) 
     HMC_TRY(M->X.ensure((size_t)n * kIn * 4, "mlp features"));
     HMC_TRY(M->t.ensure((size_t)n * 4, "mlp outputs"));
     HMC_HIP(hipMemcpyAsync(M->X.p, X, (size_t)n * kIn * 4, hipMemcpyHostToDevice, M->stream));
-    predict_kernel<<<(unsigned)((n + kPredThreads - 1) / kPredThreads), kPredThreads, 0, M->stream>>>(
+    predict_kernel<<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
         M->theta.as<float>(), M->X.as<float>(), n, 0.0, 1.0, nullptr, M->t.as<float>());
     HMC_HIP(hipGetLastError());
     HMC_HIP(hipMemcpyAsync(y_out, M->t.p, (size_t)n * 4, hipMemcpyDeviceToHost, M->stream));
@@ -578,7 +603,7 @@ hmc_status hmc_mlp_infer(hmc_mlp* M, const float* X_dev, float* y_dev, int64_t n
         HMC_HIP(hipEventRecord(M->ready, M->stream));
         HMC_HIP(hipStreamWaitEvent(s, M->ready, 0));
     }
-    predict_kernel<<<(unsigned)((n + kPredThreads - 1) / kPredThreads), kPredThreads, 0, s>>>(
+    predict_kernel<<<predict_blocks(n), kPredThreads, 0, s>>>(
         M->theta.as<float>(), X_dev, n, 0.0, 1.0, nullptr, y_dev);
     HMC_HIP(hipGetLastError());
     return HMC_OK;
@@ -627,7 +652,7 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
                                                                             W->X.as<float>());
         e = hipGetLastError();
         if (e == hipSuccess) {
-            predict_kernel<<<(unsigned)((Q + kPredThreads - 1) / kPredThreads), kPredThreads, 0, W->stream>>>(
+            predict_kernel<<<predict_blocks(Q), kPredThreads, 0, W->stream>>>(
                 W->theta.as<float>(), W->X.as<float>(), Q, W->mean, W->sdev, W->E.as<double>(), nullptr);
             e = hipGetLastError();
         }
