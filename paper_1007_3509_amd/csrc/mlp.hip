@@ -296,6 +296,31 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host memory: the destination of a query's read-backs, which from
+// pageable memory go through a staged copy.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hmc_status ensure(size_t b, const char* what) {
+        if (b <= bytes) return HMC_OK;
+        release();
+        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return hip_fail(e, what);
+        }
+        bytes = b;
+        return HMC_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
 uint32_t philox_u32(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag) {
     uint32_t o[4];
     philox4x32_10(a, b, 0u, tag, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), o);
@@ -311,6 +336,7 @@ struct hmc_mlp_s {
     int64_t step = 0;
     double mean = 0.0, sdev = 1.0;
     DevBuf X, t, partial, sel, loss, grad, euler, eps, E, Eaudit, Bq, audit_idx;
+    HostBuf readback;   // a query's predictions, audit energies and quantised energies
 };
 
 namespace {
@@ -395,6 +421,7 @@ hmc_status hmc_mlp_free(hmc_mlp* M) {
     for (DevBuf* b : {&M->theta, &M->m, &M->v, &M->X, &M->t, &M->partial, &M->sel, &M->loss, &M->grad, &M->euler,
                       &M->eps, &M->E, &M->Eaudit, &M->Bq, &M->audit_idx})
         b->release();
+    M->readback.release();
     if (M->ready) (void)hipEventDestroy(M->ready);
     (void)hipStreamDestroy(M->stream);
     delete M;
@@ -626,6 +653,12 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     hmc_mlp* W = M;
     hmc_mlp scratch_holder;   // buffers when no network is given
     if (!W) W = &scratch_holder;
+    struct ReleaseAtExit {    // the holder's read-back memory, once the energies are set
+        HostBuf* b;
+        ~ReleaseAtExit() {
+            if (b) b->release();
+        }
+    } release_readback{W == &scratch_holder ? &W->readback : nullptr};
     if (!W->stream) W->stream = L->stream;
     // every grain under the same strain: one 6-vector read with stride 0
     bool in_box = true;
@@ -643,23 +676,35 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     hipError_t e = hipSuccess;
     if (st == HMC_OK) e = hipMemcpyAsync(W->euler.p, euler, (size_t)Q * 24, hipMemcpyHostToDevice, W->stream);
     if (st == HMC_OK && e == hipSuccess) e = hipMemcpyAsync(W->eps.p, eps6, 48, hipMemcpyHostToDevice, W->stream);
+    if (st == HMC_OK) st = W->readback.ensure((size_t)Q * 12 + (size_t)na * 8, "query read-back");
+    double* predicted = st == HMC_OK ? W->readback.as<double>() : nullptr;
+    double* Es = predicted ? predicted + Q : nullptr;
+    int32_t* B = Es ? reinterpret_cast<int32_t*>(Es + na) : nullptr;
     bool solver = mode == 1 || !in_box;
     double err = 0.0;
     if (st == HMC_OK && e == hipSuccess && !solver) {
-        HMC_TRY(W->X.ensure((size_t)Q * kIn * 4, "mlp features"));
-        features_kernel<<<(unsigned)((Q + 255) / 256), 256, 0, W->stream>>>(W->euler.as<double>(),
-                                                                            W->eps.as<double>(), 0, Q,
-                                                                            W->X.as<float>());
-        e = hipGetLastError();
-        if (e == hipSuccess) {
+        st = W->X.ensure((size_t)Q * kIn * 4, "mlp features");
+        if (st == HMC_OK) {
+            features_kernel<<<(unsigned)((Q + 255) / 256), 256, 0, W->stream>>>(W->euler.as<double>(),
+                                                                                W->eps.as<double>(), 0, Q,
+                                                                                W->X.as<float>());
+            e = hipGetLastError();
+        }
+        if (st == HMC_OK && e == hipSuccess) {
             predict_kernel<<<predict_blocks(Q), kPredThreads, 0, W->stream>>>(
                 W->theta.as<float>(), W->X.as<float>(), Q, W->mean, W->sdev, W->E.as<double>(), nullptr);
+            e = hipGetLastError();
+        }
+        // the network's energies quantised ahead of the audit's verdict: an
+        // accepted query then needs no second round trip
+        if (st == HMC_OK && e == hipSuccess) {
+            quantise_kernel<<<(Q + 255) / 256, 256, 0, W->stream>>>(W->E.as<double>(), Q, E_scale * 65536.0,
+                                                                     W->Bq.as<int32_t>());
             e = hipGetLastError();
         }
         // audit: n_audit grains drawn with Philox, solved exactly with their
         // own random streams, i.e. the values the fallback would give them
         std::vector<int32_t> ids((size_t)na);
-        std::vector<double> predicted((size_t)Q), Es((size_t)na);
         if (st == HMC_OK && e == hipSuccess && na > 0) {
             std::vector<double> ae((size_t)na * 3);
             for (int32_t a = 0; a < na; ++a) {
@@ -673,11 +718,12 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
                 st = mcp_solve_device(d_ae, W->eps.as<double>(), na, seed, 0, d_ae + (size_t)na * 3, nullptr,
                                       W->stream, 0, W->audit_idx.as<int32_t>());
             if (st == HMC_OK && e == hipSuccess)
-                e = hipMemcpyAsync(Es.data(), d_ae + (size_t)na * 3, (size_t)na * 8, hipMemcpyDeviceToHost,
-                                   W->stream);
+                e = hipMemcpyAsync(Es, d_ae + (size_t)na * 3, (size_t)na * 8, hipMemcpyDeviceToHost, W->stream);
         }
         if (st == HMC_OK && e == hipSuccess)
-            e = hipMemcpyAsync(predicted.data(), W->E.p, (size_t)Q * 8, hipMemcpyDeviceToHost, W->stream);
+            e = hipMemcpyAsync(predicted, W->E.p, (size_t)Q * 8, hipMemcpyDeviceToHost, W->stream);
+        if (st == HMC_OK && e == hipSuccess)
+            e = hipMemcpyAsync(B, W->Bq.p, (size_t)Q * 4, hipMemcpyDeviceToHost, W->stream);
         if (st == HMC_OK && e == hipSuccess) e = hipStreamSynchronize(W->stream);
         if (st == HMC_OK && e == hipSuccess) {
             for (int32_t q = 0; q < Q; ++q)
@@ -690,23 +736,23 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     if (st == HMC_OK && e == hipSuccess && solver) {
         st = mcp_solve_device(W->euler.as<double>(), W->eps.as<double>(), Q, seed, 0, W->E.as<double>(), nullptr,
                               W->stream, 0, nullptr);
+        if (st == HMC_OK) {
+            quantise_kernel<<<(Q + 255) / 256, 256, 0, W->stream>>>(W->E.as<double>(), Q, E_scale * 65536.0,
+                                                                     W->Bq.as<int32_t>());
+            e = hipGetLastError();
+        }
+        if (st == HMC_OK && e == hipSuccess)
+            e = hipMemcpyAsync(B, W->Bq.p, (size_t)Q * 4, hipMemcpyDeviceToHost, W->stream);
+        if (st == HMC_OK && e == hipSuccess) e = hipStreamSynchronize(W->stream);
     }
-    if (st == HMC_OK && e == hipSuccess) {
-        quantise_kernel<<<(Q + 255) / 256, 256, 0, W->stream>>>(W->E.as<double>(), Q, E_scale * 65536.0,
-                                                                 W->Bq.as<int32_t>());
-        e = hipGetLastError();
-    }
-    std::vector<int32_t> B((size_t)Q);
-    if (st == HMC_OK && e == hipSuccess)
-        e = hipMemcpyAsync(B.data(), W->Bq.p, (size_t)Q * 4, hipMemcpyDeviceToHost, W->stream);
-    if (st == HMC_OK && e == hipSuccess) e = hipStreamSynchronize(W->stream);
     if (W == &scratch_holder) {
+        (void)hipStreamSynchronize(W->stream);   // no copy may still target the read-back memory
         for (DevBuf* b : {&W->X, &W->euler, &W->eps, &W->E, &W->Bq, &W->audit_idx, &W->Eaudit}) b->release();
     }
     if (st != HMC_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "surrogate update");
-    HMC_TRY(hmc_set_grain_energy(L, B.data(), Q, 0));
-    if (B_out) std::memcpy(B_out, B.data(), (size_t)Q * 4);
+    HMC_TRY(hmc_set_grain_energy(L, B, Q, 0));
+    if (B_out) std::memcpy(B_out, B, (size_t)Q * 4);
     *used_solver = solver ? 1 : 0;
     *audit_err = err;
     return HMC_OK;
