@@ -33,10 +33,14 @@
  *     0x4D435053)) words 0 (high) and 1 (low).
  *
  * Pins: the elastic response (closed-form cubic moduli), the yield point
- * (Schmid law), Eq. (4) and Eq. (2) identities, and the ordering of stored
- * energy with Schmid factor.  Parity unpinned: the post-yield stress-strain
- * path and stored energies themselves, which depend on the readings above
- * and have no published values to check against.
+ * (Schmid law), Eq. (4) and Eq. (2) identities, the ordering of stored
+ * energy with Schmid factor, single slip past yield (second-order
+ * convergence in the sub-step to the consistency condition with Voce
+ * hardening, the stress left by the return) and the Eq. (1) selection
+ * frequencies of several candidates.  Parity unpinned: the stress-strain
+ * path and stored energies once several systems compete over many
+ * sub-steps, which depend on the readings above and have no published
+ * values to check against.
  */
 #include <math.h>
 #include <stdint.h>
