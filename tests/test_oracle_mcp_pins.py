@@ -203,6 +203,50 @@ def test_selection_follows_eq1(orc):
     assert selection_pvalue(orc) > 1e-3
 
 
+# --- 3. frame invariance on multi-slip paths --------------------------------
+# Turning the sample frame by any rotation R turns the orientation into
+# g R^T and the strain into R eps R^T; the crystal-frame strain, and with it
+# every sub-step of the solve (candidates, Eq. (1) probabilities, Eq. (2)
+# picks with the same random stream, the Voce hardening and Eq. (4)), is
+# unchanged.  This holds at any path length, so it checks the long paths
+# where several systems compete, which have no closed form.
+
+def _rotated(euler, eps, R):
+    M = Rotation.from_euler("ZXZ", euler).as_matrix()          # g = M^T
+    return Rotation.from_matrix(R @ M).as_euler("ZXZ"), R @ eps @ R.T
+
+
+def _eps6(t):
+    return np.array([t[0, 0], t[1, 1], t[2, 2], t[1, 2], t[0, 2], t[0, 1]])
+
+
+def frame_problems(orc, dll=None, n=24, K=60):
+    rng = np.random.default_rng(2024)
+    out, multi = [], 0
+    for i in range(n):
+        euler = rng.uniform([0.0, 0.0, 0.0], [2 * np.pi, np.pi, 2 * np.pi])
+        A = rng.normal(size=(3, 3))
+        eps = 1.5e-3 * (A + A.T) / np.linalg.norm(A + A.T)      # several times the yield strain
+        E0, tc0, gm0, _, nc0, p0 = orc.mcp_run(euler, _eps6(eps), 7, K, sample=i, dll=dll)
+        multi += int(nc0.max() >= 2)
+        for _ in range(2):
+            R = Rotation.from_quat(rng.normal(size=4)).as_matrix()
+            euler_r, eps_r = _rotated(euler, eps, R)
+            E1, tc1, gm1, _, nc1, p1 = orc.mcp_run(euler_r, _eps6(eps_r), 7, K, sample=i, dll=dll)
+            if not (np.array_equal(p0, p1) and np.array_equal(nc0, nc1)):
+                out.append(f"crystal {i}: other candidates or picks in a turned sample frame")
+            elif not (abs(E1 - E0) <= 1e-9 * abs(E0) and abs(tc1 - tc0) <= 1e-9 * tc0
+                      and abs(gm1 - gm0) <= 1e-9 * max(gm0, 1e-30)):
+                out.append(f"crystal {i}: E {E0} vs {E1}, tau_c {tc0} vs {tc1}")
+    if multi < n // 2:
+        out.append(f"only {multi} of {n} paths had several candidates in a sub-step")
+    return out
+
+
+def test_stored_energy_is_frame_invariant_on_multislip_paths(orc):
+    assert frame_problems(orc) == []
+
+
 # --- 3. planted mistakes ----------------------------------------------------
 
 PLANTS = {
@@ -211,6 +255,8 @@ PLANTS = {
     "beta sign flipped": ("p[k] = exp(-MCP_BETA * (E[k] - Emin));", "p[k] = exp(MCP_BETA * (E[k] - Emin));"),
     "return with the wrong sign": ("sig[i][j] = str[i][j] - sgn * dg[pick] * CP[cand[pick]][i][j];",
                                    "sig[i][j] = str[i][j] + sgn * dg[pick] * CP[cand[pick]][i][j];"),
+    "crystal-frame strain transposed": ("acc += g[i][p] * es[p][q] * g[j][q];",
+                                        "acc += g[p][i] * es[p][q] * g[q][j];"),
 }
 
 
@@ -236,5 +282,6 @@ def planted(tmp_path_factory):
 @pytest.mark.parametrize("name", sorted(PLANTS))
 def test_planted_mcp_mistakes_fail_the_pins(orc, planted, name):
     dll = planted[name]
-    caught = bool(single_slip_problems(orc, dll=dll)) or selection_pvalue(orc, dll=dll) < 1e-3
+    caught = bool(single_slip_problems(orc, dll=dll)) or selection_pvalue(orc, dll=dll) < 1e-3 \
+        or bool(frame_problems(orc, dll=dll))
     assert caught, f"planted mistake not caught: {name}"
