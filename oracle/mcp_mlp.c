@@ -37,10 +37,11 @@
  * energy with Schmid factor, single slip past yield (second-order
  * convergence in the sub-step to the consistency condition with Voce
  * hardening, the stress left by the return) and the Eq. (1) selection
- * frequencies of several candidates.  Parity unpinned: the stress-strain
- * path and stored energies once several systems compete over many
- * sub-steps, which depend on the readings above and have no published
- * values to check against.
+ * frequencies of several candidates, and the invariance of long paths with
+ * several competing systems under a turn of the sample frame.  Parity
+ * unpinned: the values of those paths' stress and stored energy, which
+ * depend on the readings above and have no published values to check
+ * against.
  */
 #include <math.h>
 #include <stdint.h>
