@@ -220,13 +220,25 @@ constexpr int kPredUnits = kHid / kPredLanes;             // hidden units per la
 // Workgroups of kPredThreads lanes for n samples.
 inline unsigned predict_blocks(int64_t n) { return (unsigned)((n + kPredSamples - 1) / kPredSamples); }
 
+// A surrogate query's inputs and outputs: features formed from the grains'
+// orientations and one strain (read with stride 0) as features_kernel forms
+// them, and the energies quantised as quantise_kernel does.
+struct QueryIO {
+    const double* euler;   // n x 3
+    const double* eps;     // 6
+    double qscale;         // E_scale * 65536
+    int32_t* B;            // n
+};
+
 // Inference, four lanes per sample: each lane forms a quarter of the hidden
 // units of both layers (every unit's sum in the same order as one lane
 // alone would), the first layer is shared through LDS, and the four partial
-// output sums are added in a fixed order.
+// output sums are added in a fixed order.  kQuery: the features and the
+// quantised energies of a surrogate query in the same launch (q).
+template <bool kQuery>
 __global__ void __launch_bounds__(kPredThreads)
 predict_kernel(const float* __restrict__ theta, const float* __restrict__ X, int64_t n, double mean, double sdev,
-               double* __restrict__ E_out, float* __restrict__ y_std_out) {
+               double* __restrict__ E_out, float* __restrict__ y_std_out, QueryIO q) {
     __shared__ float W[kNP];
     __shared__ float H1[kPredSamples][kHid];
     for (int p = threadIdx.x; p < kNP; p += blockDim.x) W[p] = theta[p];
@@ -235,7 +247,15 @@ predict_kernel(const float* __restrict__ theta, const float* __restrict__ X, int
     const int64_t s = (int64_t)blockIdx.x * kPredSamples + ls;
     const bool live = s < n;
     float x[kIn];
-    for (int j = 0; j < kIn; ++j) x[j] = live ? X[s * kIn + j] : 0.0f;
+    if constexpr (kQuery) {
+        const double* e = q.euler + 3 * (live ? s : 0);
+        x[0] = (float)(e[0] / kPi - 1.0);
+        x[1] = (float)(2.0 * e[1] / kPi - 1.0);
+        x[2] = (float)(e[2] / kPi - 1.0);
+        for (int k = 0; k < 6; ++k) x[3 + k] = (float)(q.eps[k] / kStrainBox);
+    } else {
+        for (int j = 0; j < kIn; ++j) x[j] = live ? X[s * kIn + j] : 0.0f;
+    }
 #pragma unroll
     for (int q = 0; q < kPredUnits; ++q) {
         const int i = part * kPredUnits + q;
@@ -265,7 +285,9 @@ predict_kernel(const float* __restrict__ theta, const float* __restrict__ X, int
     if (!live || part != 0) return;
     const float out = ((W[ob3] + y) + y1) + (y2 + y3);
     if (y_std_out) y_std_out[s] = out;
-    if (E_out) E_out[s] = (double)out * sdev + mean;
+    const double E = (double)out * sdev + mean;
+    if (E_out) E_out[s] = E;
+    if constexpr (kQuery) q.B[s] = (int32_t)rint(E * q.qscale);   // round half to even
 }
 
 __global__ void quantise_kernel(const double* __restrict__ E, int32_t n, double scale, int32_t* __restrict__ B) {
@@ -595,8 +617,8 @@ hmc_status hmc_mlp_predict(hmc_mlp* M, const double* euler, const double* eps, i
         HMC_TRY(M->E.ensure((size_t)n * 8, "mlp predictions"));
         dout = M->E.as<double>();
     }
-    predict_kernel<<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
-        M->theta.as<float>(), M->X.as<float>(), n, M->mean, M->sdev, dout, nullptr);
+    predict_kernel<false><<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
+        M->theta.as<float>(), M->X.as<float>(), n, M->mean, M->sdev, dout, nullptr, QueryIO{});
     HMC_HIP(hipGetLastError());
     if (!on_device) HMC_HIP(hipMemcpyAsync(E_out, dout, (size_t)n * 8, hipMemcpyDeviceToHost, M->stream));
     HMC_HIP(hipStreamSynchronize(M->stream));
@@ -610,8 +632,8 @@ hmc_status hmc_mlp_forward(hmc_mlp* M, const float* X, int32_t n, float* y_out) 
     HMC_TRY(M->X.ensure((size_t)n * kIn * 4, "mlp features"));
     HMC_TRY(M->t.ensure((size_t)n * 4, "mlp outputs"));
     HMC_HIP(hipMemcpyAsync(M->X.p, X, (size_t)n * kIn * 4, hipMemcpyHostToDevice, M->stream));
-    predict_kernel<<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
-        M->theta.as<float>(), M->X.as<float>(), n, 0.0, 1.0, nullptr, M->t.as<float>());
+    predict_kernel<false><<<predict_blocks(n), kPredThreads, 0, M->stream>>>(
+        M->theta.as<float>(), M->X.as<float>(), n, 0.0, 1.0, nullptr, M->t.as<float>(), QueryIO{});
     HMC_HIP(hipGetLastError());
     HMC_HIP(hipMemcpyAsync(y_out, M->t.p, (size_t)n * 4, hipMemcpyDeviceToHost, M->stream));
     HMC_HIP(hipStreamSynchronize(M->stream));
@@ -630,8 +652,8 @@ hmc_status hmc_mlp_infer(hmc_mlp* M, const float* X_dev, float* y_dev, int64_t n
         HMC_HIP(hipEventRecord(M->ready, M->stream));
         HMC_HIP(hipStreamWaitEvent(s, M->ready, 0));
     }
-    predict_kernel<<<predict_blocks(n), kPredThreads, 0, s>>>(
-        M->theta.as<float>(), X_dev, n, 0.0, 1.0, nullptr, y_dev);
+    predict_kernel<false><<<predict_blocks(n), kPredThreads, 0, s>>>(
+        M->theta.as<float>(), X_dev, n, 0.0, 1.0, nullptr, y_dev, QueryIO{});
     HMC_HIP(hipGetLastError());
     return HMC_OK;
 }
@@ -683,23 +705,12 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     bool solver = mode == 1 || !in_box;
     double err = 0.0;
     if (st == HMC_OK && e == hipSuccess && !solver) {
-        st = W->X.ensure((size_t)Q * kIn * 4, "mlp features");
-        if (st == HMC_OK) {
-            features_kernel<<<(unsigned)((Q + 255) / 256), 256, 0, W->stream>>>(W->euler.as<double>(),
-                                                                                W->eps.as<double>(), 0, Q,
-                                                                                W->X.as<float>());
-            e = hipGetLastError();
-        }
-        if (st == HMC_OK && e == hipSuccess) {
-            predict_kernel<<<predict_blocks(Q), kPredThreads, 0, W->stream>>>(
-                W->theta.as<float>(), W->X.as<float>(), Q, W->mean, W->sdev, W->E.as<double>(), nullptr);
-            e = hipGetLastError();
-        }
-        // the network's energies quantised ahead of the audit's verdict: an
-        // accepted query then needs no second round trip
-        if (st == HMC_OK && e == hipSuccess) {
-            quantise_kernel<<<(Q + 255) / 256, 256, 0, W->stream>>>(W->E.as<double>(), Q, E_scale * 65536.0,
-                                                                     W->Bq.as<int32_t>());
+        // features, inference and the energies quantised in one launch, ahead
+        // of the audit's verdict: an accepted query needs no second round trip
+        {
+            const QueryIO q{W->euler.as<double>(), W->eps.as<double>(), E_scale * 65536.0, W->Bq.as<int32_t>()};
+            predict_kernel<true><<<predict_blocks(Q), kPredThreads, 0, W->stream>>>(
+                W->theta.as<float>(), nullptr, Q, W->mean, W->sdev, W->E.as<double>(), nullptr, q);
             e = hipGetLastError();
         }
         // audit: n_audit grains drawn with Philox, solved exactly with their
