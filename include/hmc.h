@@ -476,7 +476,10 @@ hmc_status hmc_mcp_solve(const double *euler, const double *eps, int64_t n, uint
                          int32_t on_device, double *E_out, double *tauc_out);
 
 /* 9-64-64-1 tanh network predicting E_rho from (Bunge angles, strain).
- * Features phi1/pi - 1, 2 Phi/pi - 1, phi2/pi - 1, e_ij / 2e-3; target
+ * Features: the Rodrigues vector of the orientation's equivalent under the
+ * 24 cubic crystal rotations with the smallest rotation angle (the cubic
+ * fundamental zone), over sqrt 2 - 1, then e_ij / 2e-3; so orientations
+ * that differ by a crystal symmetry get the same prediction.  Target
  * standardised by the training mean and standard deviation (kept in the
  * handle).  Parameters (4865 floats): W1[64][9], b1[64], W2[64][64], b2[64],
  * w3[64], b3.  create: Xavier-uniform weights from Philox(seed), zero

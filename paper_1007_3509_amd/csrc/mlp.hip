@@ -7,9 +7,10 @@
 // which enters Eq. (7) as the grain's bulk energy (Sec. 3, Sec. 6).
 //
 // Inputs: Bunge angles (phi1, Phi, phi2) and the six strain components
-// (e11, e22, e33, e23, e13, e12); features phi1/pi - 1, 2 Phi/pi - 1,
-// phi2/pi - 1, e_ij / 2e-3, so the training box [0,2pi)x[0,pi]x[0,2pi) x
-// [-2e-3, 2e-3]^6 maps to [-1,1]^9.  Target: E_rho standardised by the
+// (e11, e22, e33, e23, e13, e12); features: the Rodrigues vector of the
+// orientation's cubic-symmetry equivalent in the fundamental zone, over
+// sqrt 2 - 1, and e_ij / 2e-3, so every orientation and the strain box
+// [-2e-3, 2e-3]^6 map into [-1,1]^9.  Target: E_rho standardised by the
 // training mean and standard deviation.  Loss: mean squared error.  Adam
 // (Kingma & Ba, 2015), beta1 0.9, beta2 0.999, eps 1e-8; Xavier-uniform
 // initial weights from Philox; learning rate decays on a cosine to 1/10.
@@ -52,14 +53,54 @@ constexpr double kPi = 3.14159265358979323846;
 
 // ------------------------------------------------------------------ kernels
 
+// The orientation's three inputs: the Rodrigues vector of its cubic
+// symmetry-equivalent with the smallest rotation angle (the cubic
+// fundamental zone), scaled by 1/(sqrt 2 - 1) into [-1, 1].  The stored
+// energy depends on the orientation only up to the 24 rotations of the cubic
+// crystal (they permute the slip systems and leave the stiffness alone), so
+// the network learns it on one zone, where it has no copies and no wrap.
+__device__ __forceinline__ void orientation_features(const double* e, float* x) {
+    const double c1 = cos(e[0]), s1 = sin(e[0]), c = cos(e[1]), sn = sin(e[1]), c2 = cos(e[2]), s2 = sin(e[2]);
+    // Bunge passive matrix (crystal <- sample)
+    const double g[3][3] = {{c1 * c2 - s1 * s2 * c, s1 * c2 + c1 * s2 * c, s2 * sn},
+                            {-c1 * s2 - s1 * c2 * c, -s1 * s2 + c1 * c2 * c, c2 * sn},
+                            {s1 * sn, -c1 * sn, c}};
+    // the cubic rotation S (a signed permutation, det +1) with the largest
+    // trace of S g: rows of S g are sign[i] * row perm[i] of g
+    const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+    double best = -4.0;
+    int bp = 0, bs = 0;
+    for (int p = 0; p < 6; ++p) {
+        const int parity = p < 3 ? 1 : -1;
+        for (int sg = 0; sg < 8; ++sg) {
+            const int a = (sg & 1) ? -1 : 1, b = (sg & 2) ? -1 : 1, d = (sg & 4) ? -1 : 1;
+            if (a * b * d * parity != 1) continue;
+            const double tr = a * g[perms[p][0]][0] + b * g[perms[p][1]][1] + d * g[perms[p][2]][2];
+            if (tr > best) {
+                best = tr;
+                bp = p;
+                bs = sg;
+            }
+        }
+    }
+    const double sgn[3] = {(bs & 1) ? -1.0 : 1.0, (bs & 2) ? -1.0 : 1.0, (bs & 4) ? -1.0 : 1.0};
+    double h[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) h[i][j] = sgn[i] * g[perms[bp][i]][j];
+    // Rodrigues vector n tan(theta/2) = (antisymmetric part) / (1 + trace)
+    const double den = 1.0 + best;
+    const double k = 1.0 / (0.41421356237309503 * den);
+    x[0] = (float)((h[2][1] - h[1][2]) * k);
+    x[1] = (float)((h[0][2] - h[2][0]) * k);
+    x[2] = (float)((h[1][0] - h[0][1]) * k);
+}
+
 __global__ void features_kernel(const double* __restrict__ euler, const double* __restrict__ eps, int eps_stride,
                                 int64_t n, float* __restrict__ X) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     float* x = X + kIn * s;
-    x[0] = (float)(euler[3 * s + 0] / kPi - 1.0);
-    x[1] = (float)(2.0 * euler[3 * s + 1] / kPi - 1.0);
-    x[2] = (float)(euler[3 * s + 2] / kPi - 1.0);
+    orientation_features(euler + 3 * s, x);
     for (int k = 0; k < 6; ++k) x[3 + k] = (float)(eps[(int64_t)eps_stride * s + k] / kStrainBox);
 }
 
@@ -249,9 +290,7 @@ predict_kernel(const float* __restrict__ theta, const float* __restrict__ X, int
     float x[kIn];
     if constexpr (kQuery) {
         const double* e = q.euler + 3 * (live ? s : 0);
-        x[0] = (float)(e[0] / kPi - 1.0);
-        x[1] = (float)(2.0 * e[1] / kPi - 1.0);
-        x[2] = (float)(e[2] / kPi - 1.0);
+        orientation_features(e, x);
         for (int k = 0; k < 6; ++k) x[3 + k] = (float)(q.eps[k] / kStrainBox);
     } else {
         for (int j = 0; j < kIn; ++j) x[j] = live ? X[s * kIn + j] : 0.0f;

@@ -12,6 +12,7 @@ surrogate driver against the CPU oracle.
 * a lattice driven by the surrogate's energies stays bit-exact with the
   oracle fed the same integer energies.
 """
+import itertools
 import os
 import time
 
@@ -116,6 +117,52 @@ def test_training_learns_and_is_faster_than_the_solver():
         say(f"[gpu] solver {1e3 * (t1 - t0):.2f} ms, network {1e3 * (t2 - t1):.2f} ms, "
             f"median rel err on the query {np.median(np.abs(Em - Es) / Es):.4f}")
         assert t2 - t1 < t1 - t0
+    finally:
+        hmc.hmc_mlp_free(M)
+
+
+def _cubic_rotations():
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1.0, -1.0), repeat=3):
+            S = np.zeros((3, 3))
+            for i in range(3):
+                S[i, perm[i]] = signs[i]
+            if np.linalg.det(S) > 0:
+                out.append(S)
+    return out
+
+
+def test_crystal_symmetric_orientations_get_the_same_prediction():
+    """The stored energy does not change under the cubic crystal's 24
+    rotations (they permute the slip systems, the stiffness is cubic), and
+    the network sees the orientation through its fundamental-zone
+    equivalent: orientations g and S g (S a cubic rotation acting on the
+    crystal frame) get the same prediction, and the solver agrees up to its
+    own random streams."""
+    from scipy.spatial.transform import Rotation
+    rots = _cubic_rotations()
+    assert len(rots) == 24
+    n = 2000
+    rng = np.random.default_rng(17)
+    euler, eps = synth.crystal_inputs(n, 21)
+    g = Rotation.from_euler("ZXZ", euler).as_matrix().transpose(0, 2, 1)   # Bunge, passive
+    S = np.stack([rots[i] for i in rng.integers(1, 24, n)])
+    gs = np.einsum("nij,njk->nik", S, g)
+    euler_s = Rotation.from_matrix(gs.transpose(0, 2, 1)).as_euler("ZXZ") % (2 * np.pi)
+    M = hmc.hmc_mlp_create(3)
+    say("[gpu] network predictions under cubic crystal rotations")
+    try:
+        th, _ = hmc.hmc_mlp_get_params(M)
+        hmc.hmc_mlp_set_params(M, th, [0.0017, 0.0003])
+        a = hmc.hmc_mlp_predict(M, euler, eps)
+        b = hmc.hmc_mlp_predict(M, euler_s, eps)
+        # the same zone representative up to the rounding of the angles
+        assert np.allclose(a, b, rtol=1e-5, atol=0.0)
+        Ea = hmc.hmc_mcp_solve(euler[:200], eps[:200], seed=1)
+        Eb = hmc.hmc_mcp_solve(euler_s[:200], eps[:200], seed=1)
+        rel = np.abs(Ea - Eb) / Ea
+        assert np.median(rel) < 0.01   # the solver's own spread over random streams is about 0.24 %
     finally:
         hmc.hmc_mlp_free(M)
 
