@@ -745,7 +745,7 @@ hmc_status hmc_surrogate_update(hmc_lattice* L, hmc_mlp* M, const double* euler,
     double err = 0.0;
     if (st == HMC_OK && e == hipSuccess && !solver) {
         // features, inference and the energies quantised in one launch, ahead
-        // of the audit's verdict: an accepted query needs no second round trip
+        // of the audit's decision: an accepted query needs no second round trip
         {
             const QueryIO q{W->euler.as<double>(), W->eps.as<double>(), E_scale * 65536.0, W->Bq.as<int32_t>()};
             predict_kernel<true><<<predict_blocks(Q), kPredThreads, 0, W->stream>>>(
